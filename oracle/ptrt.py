@@ -1,0 +1,205 @@
+"""ctypes front end of the C oracle (``ptrt_oracle.c``).  Test infrastructure.
+
+Arrays cross the boundary in the layout the C-ABI of the GPU library also
+uses for host data: populations ``[Q][nz][ny][nx]``, density ``[nz][ny][nx]``,
+velocity ``[3][nz][ny][nx]`` (component-major), solid mask ``uint8
+[nz][ny][nx]`` with 1 = solid.  Internally the oracle keeps ``[node][Q]``;
+the transposes happen here.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libptrt_oracle.so")
+
+D2Q9, D3Q19 = 0, 1
+_Q = {D2Q9: 9, D3Q19: 19}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_llp = ctypes.POINTER(ctypes.c_longlong)
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.ptrt_oracle_lattice.argtypes = [ctypes.c_int, _ip, _dp, _ip]
+        lib.ptrt_oracle_ghost_basis.argtypes = [ctypes.c_int, _dp, _dp]
+        lib.ptrt_oracle_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        lib.ptrt_oracle_collide.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                            ctypes.c_double, ctypes.c_double, _dp]
+        lib.ptrt_oracle_collide_tau.argtypes = lib.ptrt_oracle_collide.argtypes
+        lib.ptrt_oracle_moments.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
+        lib.ptrt_oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        _dp, _u8p, _dp, ctypes.c_int, ctypes.c_int]
+        lib.ptrt_oracle_step_sampled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                 _dp, _u8p, _dp, ctypes.c_int, _llp, _dp]
+        lib.ptrt_oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _u8p,
+                                                _dp, _dp]
+        lib.ptrt_oracle_max_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def _g3(g):
+    out = np.zeros(3, dtype=np.float64)
+    if g is not None:
+        g = np.asarray(g, dtype=np.float64).ravel()
+        out[: g.size] = g
+    return out
+
+
+def max_threads():
+    return _load().ptrt_oracle_max_threads()
+
+
+def lattice(lat):
+    """Velocities e [Q,3] (int), weights w [Q], opposite index [Q]."""
+    Q = _Q[lat]
+    e = np.zeros((Q, 3), dtype=np.intc)
+    w = np.zeros(Q, dtype=np.float64)
+    opp = np.zeros(Q, dtype=np.intc)
+    assert _load().ptrt_oracle_lattice(lat, _p(e, _ip), _p(w), _p(opp, _ip)) == Q
+    return e.astype(np.int64), w, opp.astype(np.int64)
+
+
+def ghost_basis(lat):
+    """Orthogonal ghost basis phi [NG,Q] and its weighted norms [NG]."""
+    Q = _Q[lat]
+    phi = np.zeros((3, Q))
+    nrm = np.zeros(3)
+    ng = _load().ptrt_oracle_ghost_basis(lat, _p(phi), _p(nrm))
+    return phi[:ng].copy(), nrm[:ng].copy()
+
+
+def equilibrium(lat, rho, u):
+    """f^eq for rho [n], u [n,D or 3] -> [n,Q]."""
+    rho = np.ascontiguousarray(np.asarray(rho, dtype=np.float64).ravel())
+    n = rho.size
+    u3 = np.zeros((n, 3))
+    u = np.asarray(u, dtype=np.float64).reshape(n, -1)
+    u3[:, : u.shape[1]] = u
+    out = np.zeros((n, _Q[lat]))
+    _load().ptrt_oracle_equilibrium(lat, n, _p(rho), _p(u3), _p(out))
+    return out
+
+
+def collide(lat, f, g, tau_plus, Lambda=None, tau_minus=None):
+    """P-TRT post-collision state of independent nodes, f [n,Q] -> [n,Q]."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
+    out = np.zeros_like(f)
+    g3 = _g3(g)
+    if tau_minus is not None:
+        _load().ptrt_oracle_collide_tau(lat, f.shape[0], _p(f), _p(g3), tau_plus, tau_minus, _p(out))
+    else:
+        _load().ptrt_oracle_collide(lat, f.shape[0], _p(f), _p(g3), tau_plus, Lambda, _p(out))
+    return out
+
+
+def node_moments(lat, f, g=None):
+    """rho [n], u [n,3] of independent nodes f [n,Q] (Eq. macro)."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
+    n = f.shape[0]
+    rho = np.zeros(n)
+    u3 = np.zeros((n, 3))
+    _load().ptrt_oracle_moments(lat, n, _p(f), _p(_g3(g)), _p(rho), _p(u3))
+    return rho, u3
+
+
+class Lattice:
+    """A whole lattice advanced by the oracle.
+
+    ``f`` holds the pre-collision populations at the current time, in the
+    oracle's node-major layout ``[N][Q]``.
+    """
+
+    def __init__(self, lat, nx, ny, nz, tau_plus, Lambda, g=None, solid=None,
+                 tau_minus=None, nthreads=0):
+        self.lat = lat
+        self.Q = _Q[lat]
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.tau_plus = float(tau_plus)
+        self.Lambda = float(Lambda) if Lambda is not None else 0.0
+        self.tau_minus = -1.0 if tau_minus is None else float(tau_minus)
+        self.g = _g3(g)
+        self.solid = None if solid is None else np.ascontiguousarray(
+            np.asarray(solid, dtype=np.uint8).reshape(nz, ny, nx))
+        self.nthreads = int(nthreads)
+        self.f = np.zeros((self.N, self.Q))
+        self.t = 0
+
+    # ---- state in the ABI layout -------------------------------------
+    def set_populations(self, f_qzyx):
+        f_qzyx = np.asarray(f_qzyx, dtype=np.float64).reshape((self.Q,) + self.shape)
+        self.f = np.ascontiguousarray(f_qzyx.reshape(self.Q, self.N).T)
+
+    def populations(self):
+        return np.ascontiguousarray(self.f.T).reshape((self.Q,) + self.shape)
+
+    def init_equilibrium(self, rho=None, u=None):
+        nz, ny, nx = self.shape
+        rho = np.ones(self.shape) if rho is None else np.asarray(rho, dtype=np.float64).reshape(self.shape)
+        u3 = np.zeros((3,) + self.shape)
+        if u is not None:
+            u = np.asarray(u, dtype=np.float64)
+            u3[: u.shape[0]] = u.reshape((u.shape[0],) + self.shape)
+        feq = equilibrium(self.lat, rho.ravel(), u3.reshape(3, -1).T)
+        self.f = np.ascontiguousarray(feq)
+        self.t = 0
+
+    # ---- dynamics ------------------------------------------------------
+    def step(self, n=1):
+        nz, ny, nx = self.shape
+        solid = _p(self.solid, _u8p) if self.solid is not None else None
+        rc = _load().ptrt_oracle_run(self.lat, nx, ny, nz, self.tau_plus, self.Lambda,
+                                     self.tau_minus, _p(self.g), solid, _p(self.f),
+                                     int(n), self.nthreads)
+        if rc != 0:
+            raise RuntimeError(f"oracle run failed ({rc})")
+        self.t += n
+
+    def step_sampled(self, nodes):
+        """f(t+1) at the given flat node indices, [len(nodes), Q]; state unchanged."""
+        nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64))
+        out = np.zeros((nodes.size, self.Q))
+        nz, ny, nx = self.shape
+        solid = _p(self.solid, _u8p) if self.solid is not None else None
+        _load().ptrt_oracle_step_sampled(self.lat, nx, ny, nz, self.tau_plus, self.Lambda,
+                                         _p(self.g), solid, _p(self.f), int(nodes.size),
+                                         _p(nodes, _llp), _p(out))
+        return out
+
+    # ---- observables ---------------------------------------------------
+    def moments(self):
+        """rho [nz,ny,nx], u [3,nz,ny,nx]; solid nodes report 0."""
+        rho, u3 = node_moments(self.lat, self.f, self.g)
+        if self.solid is not None:
+            s = self.solid.ravel().astype(bool)
+            rho[s] = 0.0
+            u3[s] = 0.0
+        return rho.reshape(self.shape), np.ascontiguousarray(u3.T).reshape((3,) + self.shape)
+
+    def diagnostics(self):
+        """(mass, kinetic energy) over fluid nodes."""
+        m = ctypes.c_double()
+        k = ctypes.c_double()
+        solid = _p(self.solid, _u8p) if self.solid is not None else None
+        _load().ptrt_oracle_diagnostics(self.lat, self.N, _p(self.f), _p(self.g), solid,
+                                        ctypes.byref(m), ctypes.byref(k))
+        return m.value, k.value

@@ -1,0 +1,467 @@
+/*
+ * Reference (oracle) implementation of the Purified two-relaxation-time
+ * (P-TRT) lattice Boltzmann update, plain C, FP64.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct CPU
+ * definition that the GPU kernels are checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark load it; the
+ * product library never links, loads or calls it, and it shares no code,
+ * header or table with the GPU sources.
+ *
+ * Every function follows one equation of the paper (arXiv 2602.06686,
+ * "Purified Two-Relaxation-Time Lattice Boltzmann Method") in the paper's
+ * order and notation, with no fusion or reordering beyond what the equation
+ * states.  Readings taken where the paper is silent or inconsistent:
+ *
+ *  R1 (force terms of Eq. PTRT).  The first-order part of the
+ *     non-equilibrium population is relaxed with tau_{s,1} (Sec. 2.2, the
+ *     sentence after Eq. TRT-RLB, and the order-epsilon Chapman-Enskog
+ *     equation).  Combining that term with the Scheme II source
+ *     (1 - 1/(2 tau_{s,1})) w_i e_i.F / c_s^2 gives a net source of
+ *     (1/2) w_i e_i.F / c_s^2, so the update is
+ *       f* = f^eq + (1-1/tau+) R2 + (1-1/tau-) R3 + (1/2) w_i e_i.F / c_s^2
+ *     with R3 from Eq. R3_force.  This keeps sum_i e_i f*_i = sum_i e_i f_i + F.
+ *  R2 (cubic correction G_i of Eq. Gi) is omitted: it needs a spatial
+ *     derivative of rho u^3 and vanishes for the channel flows.
+ *  R3 (D3Q19 ghost basis).  The three products (e_a^2-c_s^2)(e_b^2-c_s^2)
+ *     of Appendix A.2 are neither orthogonal to one another nor to the
+ *     stress modes under the weighted inner product.  The ghost subspace of
+ *     Eq. S_decomp is therefore spanned by those products after
+ *     Gram-Schmidt against the mass mode, the stress modes and each other
+ *     (weighted inner product sum_i w_i a_i b_i).  On D2Q9 the single
+ *     product is already orthogonal and is left unchanged.
+ *  R4 (force) F = rho g with g a constant acceleration (Sec. 3.3).
+ *  R5 (time step) collide, then stream (left side of Eq. PTRT); halfway
+ *     bounce-back sends a population whose target node is solid back into
+ *     the opposite direction of its source node (Sec. 3.3).
+ *
+ * Population layout used by this file: f[node * Q + i], node = (z*ny+y)*nx+x.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define QMAX 19
+#define NGMAX 3
+
+typedef struct {
+    int D, Q;
+    int e[QMAX][3];
+    double w[QMAX];
+    int opp[QMAX];
+    double cs2;
+    int NG;
+    double phi[NGMAX][QMAX]; /* orthogonal ghost basis, Eq. ghost_proj */
+    double Nphi[NGMAX];      /* weighted norms of the basis */
+} Lattice;
+
+/* ---------------------------------------------------------------- lattices */
+
+/* D2Q9 velocities and weights in the printed order, Eq. D2Q9. */
+static void lattice_d2q9(Lattice *L)
+{
+    static const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    L->D = 2;
+    L->Q = 9;
+    for (int i = 0; i < 9; ++i) {
+        L->e[i][0] = ex[i];
+        L->e[i][1] = ey[i];
+        L->e[i][2] = 0;
+        L->w[i] = (i == 0) ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+}
+
+/* D3Q19: one rest, six axial and twelve face-diagonal velocities (App. A.2).
+ * The paper prints neither weights nor order; the textbook weights 1/3,
+ * 1/18, 1/36 are used, in the order: rest, +x,-x,+y,-y,+z,-z, then the
+ * diagonals of the xy, xz and yz planes, each followed by its opposite. */
+static void lattice_d3q19(Lattice *L)
+{
+    static const int ev[19][3] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+        {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+        {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+        {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    L->D = 3;
+    L->Q = 19;
+    for (int i = 0; i < 19; ++i) {
+        int n2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            L->e[i][a] = ev[i][a];
+            n2 += ev[i][a] * ev[i][a];
+        }
+        L->w[i] = (n2 == 0) ? 1.0 / 3.0 : (n2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+}
+
+/* Opposite index: e_{ibar} = -e_i (text after Eq. D2Q9), found by search. */
+static void find_opposites(Lattice *L)
+{
+    for (int i = 0; i < L->Q; ++i) {
+        L->opp[i] = -1;
+        for (int j = 0; j < L->Q; ++j)
+            if (L->e[j][0] == -L->e[i][0] && L->e[j][1] == -L->e[i][1] &&
+                L->e[j][2] == -L->e[i][2])
+                L->opp[i] = j;
+    }
+}
+
+/* Weighted inner product sum_i w_i a_i b_i used throughout Sec. 2.3. */
+static double wdot(const Lattice *L, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int i = 0; i < L->Q; ++i) s += L->w[i] * a[i] * b[i];
+    return s;
+}
+
+/* ---------------------------------------------------- Hermite, Eq. Hermite */
+
+static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+static double hermite2(const Lattice *L, int i, int a, int b)
+{
+    return L->e[i][a] * L->e[i][b] - L->cs2 * kd(a, b);
+}
+
+static double hermite3(const Lattice *L, int i, int a, int b, int c)
+{
+    const int *e = L->e[i];
+    return (double)e[a] * e[b] * e[c] -
+           L->cs2 * (e[a] * kd(b, c) + e[b] * kd(c, a) + e[c] * kd(a, b));
+}
+
+/* ------------------------------------------------------- ghost basis (R3) */
+
+/* Ghost products (e_a^2 - c_s^2)(e_b^2 - c_s^2): Eq. ghost_D2Q9 and App. A.2,
+ * orthogonalised (Gram-Schmidt, weighted inner product) against the mass
+ * mode, the D(D+1)/2 stress modes H^(2)_{ab} and each other; reading R3. */
+static void build_ghost_basis(Lattice *L)
+{
+    double basis[1 + 6 + NGMAX][QMAX];
+    int nb = 0;
+    int Q = L->Q, D = L->D;
+
+    /* hydrodynamic symmetric modes: 1 and H^(2)_{ab}, a <= b (Eq. S_decomp) */
+    for (int i = 0; i < Q; ++i) basis[nb][i] = 1.0;
+    nb++;
+    for (int a = 0; a < D; ++a)
+        for (int b = a; b < D; ++b) {
+            for (int i = 0; i < Q; ++i) basis[nb][i] = hermite2(L, i, a, b);
+            nb++;
+        }
+    int nhydro = nb;
+
+    /* ghost products in the paper's order: (x,y), then (y,z), (z,x) */
+    static const int pairs[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+    L->NG = (D == 2) ? 1 : 3;
+    for (int k = 0; k < L->NG; ++k) {
+        int a = pairs[k][0], b = pairs[k][1];
+        for (int i = 0; i < Q; ++i)
+            basis[nb][i] = (L->e[i][a] * L->e[i][a] - L->cs2) *
+                           (L->e[i][b] * L->e[i][b] - L->cs2);
+        nb++;
+    }
+
+    /* classical Gram-Schmidt with re-orthogonalisation, done twice */
+    for (int m = 0; m < nb; ++m) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int n = 0; n < m; ++n) {
+                double c = wdot(L, basis[m], basis[n]) / wdot(L, basis[n], basis[n]);
+                for (int i = 0; i < Q; ++i) basis[m][i] -= c * basis[n][i];
+            }
+    }
+    for (int k = 0; k < L->NG; ++k) {
+        for (int i = 0; i < Q; ++i) L->phi[k][i] = basis[nhydro + k][i];
+        L->Nphi[k] = wdot(L, L->phi[k], L->phi[k]);
+    }
+}
+
+static int make_lattice(int id, Lattice *L)
+{
+    memset(L, 0, sizeof(*L));
+    if (id == 0)
+        lattice_d2q9(L);
+    else if (id == 1)
+        lattice_d3q19(L);
+    else
+        return -1;
+    L->cs2 = 1.0 / 3.0;
+    find_opposites(L);
+    build_ghost_basis(L);
+    return 0;
+}
+
+/* ------------------------------------------------------ per-node operators */
+
+/* Eq. macro with F = rho g (R4): rho = sum f, rho u = sum e f + F/2. */
+static void moments(const Lattice *L, const double *f, const double g[3],
+                    double *rho, double u[3])
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < L->Q; ++i) {
+        r += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += L->e[i][a] * f[i];
+    }
+    *rho = r;
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * r * g[a]) / r;
+}
+
+/* Eq. feq: third-order Hermite equilibrium, every tensor term summed. */
+static void equilibrium(const Lattice *L, double rho, const double u[3], double *feq)
+{
+    int D = L->D;
+    double cs2 = L->cs2, cs4 = cs2 * cs2, cs6 = cs4 * cs2;
+    for (int i = 0; i < L->Q; ++i) {
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            t1 += L->e[i][a] * u[a];
+            for (int b = 0; b < D; ++b) {
+                t2 += hermite2(L, i, a, b) * u[a] * u[b];
+                for (int c = 0; c < D; ++c) t3 += hermite3(L, i, a, b, c) * u[a] * u[b] * u[c];
+            }
+        }
+        feq[i] = L->w[i] * rho * (1.0 + t1 / cs2 + t2 / (2.0 * cs4) + t3 / (6.0 * cs6));
+    }
+}
+
+/* Eq. fneq_parity: symmetric and antisymmetric halves. */
+static void parity_split(const Lattice *L, const double *fneq, double *plus, double *minus)
+{
+    for (int i = 0; i < L->Q; ++i) {
+        plus[i] = 0.5 * (fneq[i] + fneq[L->opp[i]]);
+        minus[i] = 0.5 * (fneq[i] - fneq[L->opp[i]]);
+    }
+}
+
+/* Eq. ghost_proj: (P^G f)_i = sum_k w_i phi_ik / N_k * sum_j phi_jk f_j. */
+static void ghost_projection(const Lattice *L, const double *fneq, double *pg)
+{
+    for (int i = 0; i < L->Q; ++i) pg[i] = 0.0;
+    for (int k = 0; k < L->NG; ++k) {
+        double S = 0.0; /* ghost scalar moment S_{G,k} */
+        for (int j = 0; j < L->Q; ++j) S += L->phi[k][j] * fneq[j];
+        for (int i = 0; i < L->Q; ++i) pg[i] += L->w[i] * L->phi[k][i] / L->Nphi[k] * S;
+    }
+}
+
+/* One P-TRT collision, Eq. PTRT with R1: f -> f*. */
+static void collide(const Lattice *L, const double *f, const double g[3],
+                    double tau_p, double tau_m, double *fstar)
+{
+    double rho, u[3], feq[QMAX], fneq[QMAX], plus[QMAX], minus[QMAX], pg[QMAX];
+    moments(L, f, g, &rho, u);
+    equilibrium(L, rho, u, feq);
+    for (int i = 0; i < L->Q; ++i) fneq[i] = f[i] - feq[i];
+    parity_split(L, fneq, plus, minus);
+    ghost_projection(L, fneq, pg);
+    double F[3] = {rho * g[0], rho * g[1], rho * g[2]};
+    for (int i = 0; i < L->Q; ++i) {
+        double eF = L->e[i][0] * F[0] + L->e[i][1] * F[1] + L->e[i][2] * F[2];
+        double half_force = 0.5 * L->w[i] * eF / L->cs2;
+        double R2 = plus[i] - pg[i];           /* Theorem 2, Eq. R2_D2Q9 */
+        double R3 = minus[i] + half_force;     /* Eq. R3_force */
+        fstar[i] = feq[i] + (1.0 - 1.0 / tau_p) * R2 + (1.0 - 1.0 / tau_m) * R3 + half_force;
+    }
+}
+
+/* tau_{s,2} from the magic parameter Lambda = (tau+ - 1/2)(tau- - 1/2). */
+static double tau_minus_from_lambda(double tau_p, double Lambda)
+{
+    return 0.5 + Lambda / (tau_p - 0.5);
+}
+
+/* ------------------------------------------------------------ public API */
+
+int ptrt_oracle_lattice(int id, int *e_out, double *w_out, int *opp_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    for (int i = 0; i < L.Q; ++i) {
+        for (int a = 0; a < 3; ++a) e_out[3 * i + a] = L.e[i][a];
+        w_out[i] = L.w[i];
+        opp_out[i] = L.opp[i];
+    }
+    return L.Q;
+}
+
+/* Orthogonal ghost basis [NG][Q] and its weighted norms; returns NG. */
+int ptrt_oracle_ghost_basis(int id, double *phi_out, double *norm_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    for (int k = 0; k < L.NG; ++k) {
+        for (int i = 0; i < L.Q; ++i) phi_out[k * L.Q + i] = L.phi[k][i];
+        norm_out[k] = L.Nphi[k];
+    }
+    return L.NG;
+}
+
+int ptrt_oracle_equilibrium(int id, int n, const double *rho, const double *u3,
+                            double *feq_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    for (int m = 0; m < n; ++m) equilibrium(&L, rho[m], u3 + 3 * m, feq_out + (size_t)m * L.Q);
+    return 0;
+}
+
+/* Collide n independent nodes (f_in [n][Q]) -> f_out [n][Q]. */
+int ptrt_oracle_collide(int id, int n, const double *f_in, const double g[3],
+                        double tau_plus, double Lambda, double *f_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    double tau_m = tau_minus_from_lambda(tau_plus, Lambda);
+    for (int m = 0; m < n; ++m)
+        collide(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_m, f_out + (size_t)m * L.Q);
+    return 0;
+}
+
+/* Same with tau_{s,2} given directly (used where Lambda is not the input). */
+int ptrt_oracle_collide_tau(int id, int n, const double *f_in, const double g[3],
+                            double tau_plus, double tau_minus, double *f_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    for (int m = 0; m < n; ++m)
+        collide(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_minus, f_out + (size_t)m * L.Q);
+    return 0;
+}
+
+/* Moments of every node: rho [N], u [N][3] (Eq. macro). */
+int ptrt_oracle_moments(int id, int n, const double *f, const double g[3],
+                        double *rho, double *u3)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    for (int m = 0; m < n; ++m) moments(&L, f + (size_t)m * L.Q, g, rho + m, u3 + 3 * m);
+    return 0;
+}
+
+static size_t node_index(int x, int y, int z, int nx, int ny)
+{
+    return ((size_t)z * ny + y) * nx + x;
+}
+
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/*
+ * Advance f [N][Q] (pre-collision populations at time t) by nsteps steps:
+ * collide every fluid node (Eq. PTRT, R1), then stream with periodic wrap
+ * and halfway bounce-back at solid neighbours (R5).  Populations stored at
+ * solid nodes are not touched.  tau_minus <= 0 means "derive from Lambda".
+ */
+int ptrt_oracle_run(int id, int nx, int ny, int nz, double tau_plus, double Lambda,
+                    double tau_minus, const double g[3], const uint8_t *solid,
+                    double *f, int nsteps, int nthreads)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    if (id == 0 && nz != 1) return -2;
+    double tau_m = tau_minus > 0.0 ? tau_minus : tau_minus_from_lambda(tau_plus, Lambda);
+    int Q = L.Q;
+    size_t N = (size_t)nx * ny * nz;
+    double *fstar = (double *)malloc(N * Q * sizeof(double));
+    if (!fstar) return -3;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    for (int step = 0; step < nsteps; ++step) {
+        /* collision */
+#pragma omp parallel for schedule(static)
+        for (long long m = 0; m < (long long)N; ++m) {
+            if (solid && solid[m]) continue;
+            collide(&L, f + m * Q, g, tau_plus, tau_m, fstar + m * Q);
+        }
+        /* streaming, left side of Eq. PTRT, with halfway bounce-back */
+#pragma omp parallel for schedule(static)
+        for (long long m = 0; m < (long long)N; ++m) {
+            if (solid && solid[m]) continue;
+            int x = (int)(m % nx), y = (int)((m / nx) % ny), z = (int)(m / ((size_t)nx * ny));
+            for (int i = 0; i < Q; ++i) {
+                int xn = wrap(x + L.e[i][0], nx), yn = wrap(y + L.e[i][1], ny),
+                    zn = wrap(z + L.e[i][2], nz);
+                size_t t = node_index(xn, yn, zn, nx, ny);
+                if (solid && solid[t])
+                    f[(size_t)m * Q + L.opp[i]] = fstar[(size_t)m * Q + i];
+                else
+                    f[t * Q + i] = fstar[(size_t)m * Q + i];
+            }
+        }
+    }
+    free(fstar);
+    return 0;
+}
+
+/*
+ * One step evaluated only at the listed nodes: out[s][i] = f_i(x_s, t+1)
+ * for the pre-collision state f at time t.  Each sampled population is
+ * obtained from the collision at its source node x_s - e_i, or at x_s itself
+ * with the opposite direction when that source is solid (R5).  Used to check
+ * lattices too large for a whole-lattice oracle run.
+ */
+int ptrt_oracle_step_sampled(int id, int nx, int ny, int nz, double tau_plus,
+                             double Lambda, const double g[3], const uint8_t *solid,
+                             const double *f, int nsample, const long long *nodes,
+                             double *out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    double tau_m = tau_minus_from_lambda(tau_plus, Lambda);
+    int Q = L.Q;
+#pragma omp parallel for schedule(static)
+    for (int s = 0; s < nsample; ++s) {
+        long long m = nodes[s];
+        int x = (int)(m % nx), y = (int)((m / nx) % ny), z = (int)(m / ((long long)nx * ny));
+        double fs[QMAX];
+        for (int i = 0; i < Q; ++i) {
+            int xs = wrap(x - L.e[i][0], nx), ys = wrap(y - L.e[i][1], ny),
+                zs = wrap(z - L.e[i][2], nz);
+            size_t src = node_index(xs, ys, zs, nx, ny);
+            if (solid && solid[src]) {
+                collide(&L, f + (size_t)m * Q, g, tau_plus, tau_m, fs);
+                out[(size_t)s * Q + i] = fs[L.opp[i]];
+            } else {
+                collide(&L, f + src * Q, g, tau_plus, tau_m, fs);
+                out[(size_t)s * Q + i] = fs[i];
+            }
+        }
+    }
+    return 0;
+}
+
+/* Mass and kinetic energy over fluid nodes: sum rho, (1/2) sum rho |u|^2. */
+int ptrt_oracle_diagnostics(int id, int n, const double *f, const double g[3],
+                            const uint8_t *solid, double *mass, double *kinetic)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    double M = 0.0, K = 0.0;
+    for (int m = 0; m < n; ++m) {
+        if (solid && solid[m]) continue;
+        double rho, u[3];
+        moments(&L, f + (size_t)m * L.Q, g, &rho, u);
+        M += rho;
+        K += 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    }
+    *mass = M;
+    *kinetic = K;
+    return 0;
+}
+
+int ptrt_oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
