@@ -1,0 +1,228 @@
+/*
+ * ptrt.h -- C interface of libptrt, the MI355X (gfx950) implementation of the
+ * Purified two-relaxation-time (P-TRT) lattice Boltzmann update of
+ * arXiv 2602.06686 ("Purified Two-Relaxation-Time Lattice Boltzmann Method:
+ * Removing Ghost Modes from TRT for Enhanced Stability").
+ *
+ * One call of ptrt_step advances a lattice by the fused per-node update of
+ * Eq. PTRT: pull-streaming with halfway bounce-back at solid links (Sec. 3.3),
+ * density and half-force velocity (Eq. macro), the third-order Hermite
+ * equilibrium (Eq. feq), the parity split of the non-equilibrium part
+ * (Eq. fneq_parity), algebraic removal of the ghost modes (Theorem 2,
+ * Eq. ghost_proj; one mode on D2Q9, three on D3Q19), and relaxation with the
+ * two rates tau+ and tau- plus the body-force terms (Theorem 3, Eq. R3_force).
+ * The net force source is (1/2) w_i e_i.F / c_s^2 (the first-order moment is
+ * relaxed with tau+, as in the sentence after Eq. TRT-RLB), so each step adds
+ * exactly F to the momentum.  The cubic correction G_i of Eq. Gi is not
+ * applied.  F = rho g with a constant acceleration g (Sec. 3.3).
+ *
+ * Parameters: tau+ is the symmetric (viscous) relaxation time,
+ * nu = (tau+ - 1/2)/3 (Eq. viscosity); tau- follows from the magic parameter
+ * Lambda = (tau+ - 1/2)(tau- - 1/2) (Sec. 3.2).  Lattice units throughout
+ * (dx = dt = 1, c_s^2 = 1/3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Host arrays (all double, caller-owned, C order):
+ *   density      rho[nz][ny][nx]
+ *   velocity     u[3][nz][ny][nx]      (component-major; u[2] ignored on D2Q9)
+ *   populations  f[Q][nz][ny][nx]      (direction-major, unshifted f_i)
+ *   solid mask   uint8 [nz][ny][nx], 1 = solid, 0 = fluid
+ * The library copies what it needs during the call and keeps no caller
+ * pointer.  Device memory is owned by the library and freed by destroy.
+ *
+ * Velocity order (also returned by ptrt_velocity_set):
+ *   D2Q9  (Eq. D2Q9, printed order): (0,0) (1,0) (0,1) (-1,0) (0,-1)
+ *         (1,1) (-1,1) (-1,-1) (1,-1)
+ *   D3Q19 (App. A.2; order and weights 1/3, 1/18, 1/36 chosen here):
+ *         rest; +x -x +y -y +z -z; (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0);
+ *         (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1); (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *
+ * Time: the state is "populations at integer time t, before collision".
+ * ptrt_init_equilibrium sets f(t=0) = f^eq(rho, u) and t = 0; ptrt_step(n)
+ * advances t by n; moments, diagnostics and get_populations report the state
+ * at the current t.  Because u includes half the force (Eq. macro), the
+ * velocity reported at t = 0 is u_init + g/2.
+ *
+ * Storage: populations are kept on the GPU as shifted values
+ * f_i - w_i (reference density 1) in the storage type chosen with
+ * ptrt_set_storage: FP64 (FP64 arithmetic), FP32, FP16 or BF16 (FP32
+ * arithmetic; FP16/BF16 round to nearest even on store).
+ *
+ * Streams: work is enqueued on the stream given to ptrt_set_stream (default:
+ * the null stream).  ptrt_step is asynchronous; the calls that return host
+ * data synchronise that stream.
+ *
+ * Errors: every int-returning call returns PTRT_OK (0) or a negative code and
+ * leaves a message readable with ptrt_last_error.  A handle is not
+ * thread-safe; distinct handles are independent.  Sizes are limited to
+ * nx*ny*nz < 2^31 nodes per lattice.
+ */
+#ifndef PTRT_H
+#define PTRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptrt_ctx ptrt_ctx;
+typedef struct ptrt_batch ptrt_batch;
+
+enum ptrt_lattice { PTRT_D2Q9 = 0, PTRT_D3Q19 = 1 };
+
+enum ptrt_storage { PTRT_F64 = 0, PTRT_F32 = 1, PTRT_F16 = 2, PTRT_BF16 = 3 };
+
+enum ptrt_status {
+    PTRT_OK = 0,
+    PTRT_EINVAL = -1,    /* bad lattice id, size, pointer or argument */
+    PTRT_ETAU = -2,      /* tau+ <= 1/2, Lambda <= 0, or a non-finite parameter */
+    PTRT_ENOMEM = -3,    /* device allocation failed */
+    PTRT_EDEVICE = -4,   /* a HIP call failed (no GPU, launch error, ...) */
+    PTRT_EDIVERGED = -5, /* diagnostics found a non-finite mass or energy */
+    PTRT_ESTATE = -6     /* call not valid in the handle's current state */
+};
+
+/* ------------------------------------------------------------------------
+ * Single lattice
+ * ------------------------------------------------------------------------ */
+
+/* Create a lattice of nx*ny*nz nodes (nz must be 1 for D2Q9) with
+ * relaxation time tau_plus > 1/2 and magic parameter Lambda > 0 (Sec. 3.2),
+ * acceleration force[3] (NULL = none; force[2] ignored on D2Q9) and an
+ * optional solid mask (NULL = all fluid).  Boundaries are periodic in every
+ * direction; walls are made of solid nodes.  Storage defaults to FP32.
+ * Device memory is allocated by ptrt_init_equilibrium / ptrt_set_populations.
+ * On failure *out is NULL and the message is in ptrt_last_error(NULL). */
+int ptrt_create(int lattice, int nx, int ny, int nz, double tau_plus, double Lambda,
+                const double *force, const uint8_t *solid_mask, ptrt_ctx **out);
+
+/* Choose the storage type (enum ptrt_storage).  Only before the first init
+ * or set_populations; PTRT_ESTATE afterwards. */
+int ptrt_set_storage(ptrt_ctx *ctx, int storage);
+
+/* Stream for all later work of this handle; a hipStream_t passed as void*
+ * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */
+int ptrt_set_stream(ptrt_ctx *ctx, void *hip_stream);
+
+/* f(t=0) = f^eq(rho, u) at every fluid node (Eq. feq), computed on the GPU in
+ * FP64 and rounded to the storage type.  rho NULL = 1 everywhere, u NULL = 0.
+ * Resets the step counter to 0.  Synchronous. */
+int ptrt_init_equilibrium(ptrt_ctx *ctx, const double *rho, const double *u);
+
+/* Enqueue n >= 0 fused P-TRT steps (Eq. PTRT).  Asynchronous. */
+int ptrt_step(ptrt_ctx *ctx, int n);
+
+/* Density and half-force velocity (Eq. macro) of the state at the current
+ * time, into caller arrays rho[nz][ny][nx] and u[3][nz][ny][nx] (either may
+ * be NULL).  Solid nodes report 0.  Synchronous. */
+int ptrt_moments(ptrt_ctx *ctx, double *rho_out, double *u_out);
+
+/* Mass sum(rho) and kinetic energy (1/2) sum(rho |u|^2) over fluid nodes,
+ * reduced on the GPU in FP64.  Returns PTRT_EDIVERGED (with the values
+ * still written) if either is not finite.  Synchronous. */
+int ptrt_diagnostics(ptrt_ctx *ctx, double *mass, double *kinetic_energy);
+
+/* Copy the populations f[Q][nz][ny][nx] at the current time to the host
+ * (unshifted, FP64; solid nodes report 0).  Synchronous.  Together with
+ * ptrt_set_populations and ptrt_get_time this is a checkpoint. */
+int ptrt_get_populations(ptrt_ctx *ctx, double *f_out);
+
+/* Replace the state by f[Q][nz][ny][nx] (unshifted; values at solid nodes
+ * are ignored), rounded to the storage type.  Keeps the step counter.
+ * Synchronous. */
+int ptrt_set_populations(ptrt_ctx *ctx, const double *f_in);
+
+/* Number of steps taken since the last init. */
+int ptrt_get_time(const ptrt_ctx *ctx, long long *t_out);
+
+/* Message of the last failed call on ctx; with ctx == NULL, of the last
+ * failed ptrt_create on this thread.  Never NULL. */
+const char *ptrt_last_error(const ptrt_ctx *ctx);
+
+/* Free the handle and its device memory.  NULL is a no-op. */
+int ptrt_destroy(ptrt_ctx *ctx);
+
+/* Host-only table query: writes the Q velocities e[Q][3] and weights w[Q]
+ * of a lattice in the order used by every population array (either pointer
+ * may be NULL) and returns Q, or PTRT_EINVAL. */
+int ptrt_velocity_set(int lattice, int *e_out, double *w_out);
+
+/* Bytes of HBM traffic one node update moves (2 Q times the storage size,
+ * plus 1 for the mask when the lattice has one): the algorithmic traffic
+ * used for roofline figures. */
+double ptrt_bytes_per_node(const ptrt_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent D2Q9 lattices of different sizes, each with
+ * its own tau+, Lambda, force and mask, advanced together.  Each instance
+ * computes exactly what a single lattice with the same parameters computes,
+ * bit for bit.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int nx, ny;                  /* lattice size (nz = 1) */
+    double tau_plus, Lambda;     /* as for ptrt_create */
+    double force[3];             /* acceleration g; force[2] ignored */
+    const uint8_t *solid_mask;   /* [ny][nx] or NULL; copied during the call */
+} ptrt_instance_desc;
+
+/* Create a batch of count D2Q9 instances in one device allocation with the
+ * given storage type.  Every instance starts at rest (rho = 1, u = 0). */
+int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage,
+                      ptrt_batch **out);
+
+int ptrt_batch_set_stream(ptrt_batch *b, void *hip_stream);
+
+/* Set instance k to f^eq(rho, u) (NULL = rest); synchronous. */
+int ptrt_batch_init_equilibrium(ptrt_batch *b, int instance, const double *rho,
+                                 const double *u);
+
+/* Tile plan of the fused launch: tiles of tile_x * tile_y nodes walked by a
+ * grid of `blocks` workgroups (0 = one workgroup per tile; otherwise each
+ * workgroup takes every blocks-th tile).  tile_x * tile_y must be 64, 128,
+ * 256, 512 or 1024 with tile_x a multiple of 32.  xcd_order != 0 orders the
+ * tile list so that the workgroups the hardware sends to one of the eight
+ * accelerator dies (XCDs, round-robin by workgroup index) get neighbouring
+ * tiles, which then share that die's L2.  Rebuilds the tile table and drops
+ * any captured graph. */
+int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int xcd_order);
+
+/* Time the candidate plans on the device and keep the fastest; writes the
+ * chosen plan if the pointers are not NULL.  Runs (and so advances the batch
+ * by) a few steps per candidate.  Synchronous. */
+int ptrt_batch_autotune(ptrt_batch *b, int *tile_x, int *tile_y, int *blocks, int *xcd_order);
+
+/* Enqueue n steps, each one launch over every instance, replayed from a
+ * captured HIP graph.  Asynchronous. */
+int ptrt_batch_step(ptrt_batch *b, int n);
+
+/* Enqueue n steps as one launch per instance per step (the comparison
+ * baseline for the fused launch).  Asynchronous. */
+int ptrt_batch_step_separate(ptrt_batch *b, int n);
+
+/* Moments and populations of one instance, layouts as for a single lattice
+ * with nz = 1.  Synchronous. */
+int ptrt_batch_moments(ptrt_batch *b, int instance, double *rho_out, double *u_out);
+int ptrt_batch_get_populations(ptrt_batch *b, int instance, double *f_out);
+
+/* Mass and kinetic energy of every instance (arrays of count doubles),
+ * FP64 reduction on the GPU.  Returns PTRT_EDIVERGED if any is not finite. */
+int ptrt_batch_diagnostics(ptrt_batch *b, double *mass, double *kinetic_energy);
+
+/* Total node count of the batch (solid included) and the algorithmic bytes
+ * one step moves. */
+long long ptrt_batch_nodes(const ptrt_batch *b);
+double ptrt_batch_bytes_per_step(const ptrt_batch *b);
+
+/* As ptrt_last_error; with b == NULL, the last failed ptrt_batch_create on
+ * this thread. */
+const char *ptrt_batch_last_error(const ptrt_batch *b);
+int ptrt_batch_destroy(ptrt_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTRT_H */

@@ -307,6 +307,7 @@ int ptrt_oracle_equilibrium(int id, int n, const double *rho, const double *u3,
 {
     Lattice L;
     if (make_lattice(id, &L)) return -1;
+#pragma omp parallel for schedule(static)
     for (int m = 0; m < n; ++m) equilibrium(&L, rho[m], u3 + 3 * m, feq_out + (size_t)m * L.Q);
     return 0;
 }
@@ -340,6 +341,7 @@ int ptrt_oracle_moments(int id, int n, const double *f, const double g[3],
 {
     Lattice L;
     if (make_lattice(id, &L)) return -1;
+#pragma omp parallel for schedule(static)
     for (int m = 0; m < n; ++m) moments(&L, f + (size_t)m * L.Q, g, rho + m, u3 + 3 * m);
     return 0;
 }

@@ -1,0 +1,78 @@
+// Storage types of the shifted populations h_i = f_i - w_i and their
+// conversion to the compute type.  FP16 and BF16 round to nearest even.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptrt {
+
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <class S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+    using compute = double;
+    static constexpr int bytes = 8;
+    __device__ __forceinline__ static double load(const double *p) { return *p; }
+    __device__ __forceinline__ static double to_double(double v) { return v; }
+    __device__ __forceinline__ static void store(double *p, double v) { *p = v; }
+};
+
+template <>
+struct Codec<float> {
+    using compute = float;
+    static constexpr int bytes = 4;
+    __device__ __forceinline__ static float load(const float *p) { return *p; }
+    __device__ __forceinline__ static void store(float *p, float v) { *p = v; }
+};
+
+template <>
+struct Codec<_Float16> {
+    using compute = float;
+    static constexpr int bytes = 2;
+    __device__ __forceinline__ static float load(const _Float16 *p) { return (float)*p; }
+    __device__ __forceinline__ static void store(_Float16 *p, float v) { *p = (_Float16)v; }
+};
+
+template <>
+struct Codec<bf16_t> {
+    using compute = float;
+    static constexpr int bytes = 2;
+    __device__ __forceinline__ static float load(const bf16_t *p)
+    {
+        return __uint_as_float(((uint32_t)p->bits) << 16);
+    }
+    __device__ __forceinline__ static uint16_t encode(float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u); // NaN stays NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+    __device__ __forceinline__ static void store(bf16_t *p, float v) { p->bits = encode(v); }
+};
+
+// FP64 read of a stored value (gathers and diagnostics report in FP64).
+template <class S>
+__device__ __forceinline__ double load_f64(const S *p)
+{
+    return (double)Codec<S>::load(p);
+}
+
+// Store of an FP64 value: rounded once, directly from FP64, for FP64 and
+// FP32 storage; FP16/BF16 go through FP32 first.
+template <class S>
+__device__ __forceinline__ void store_f64(S *p, double v)
+{
+    if constexpr (sizeof(S) >= 4)
+        *p = (S)v;
+    else
+        Codec<S>::store(p, (float)v);
+}
+
+} // namespace ptrt

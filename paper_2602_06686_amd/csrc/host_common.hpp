@@ -1,0 +1,103 @@
+// Host-side helpers shared by the single-lattice and batched entry points:
+// type dispatch over (lattice, storage, mask) and launch geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "ptrt.h"
+
+namespace ptrt {
+
+template <class T>
+struct Tag {
+    using type = T;
+};
+
+// Call f(Tag<L>, Tag<S>, bool_constant<MASK>) for the runtime choice.
+template <class F>
+inline int dispatch(int lattice, int storage, bool mask, F &&f)
+{
+    auto with_lat = [&](auto lt) -> int {
+        auto with_mask = [&](auto st) -> int {
+            if (mask) return f(lt, st, std::true_type{});
+            return f(lt, st, std::false_type{});
+        };
+        switch (storage) {
+        case PTRT_F64: return with_mask(Tag<double>{});
+        case PTRT_F32: return with_mask(Tag<float>{});
+        case PTRT_F16: return with_mask(Tag<_Float16>{});
+        case PTRT_BF16: return with_mask(Tag<bf16_t>{});
+        default: return PTRT_EINVAL;
+        }
+    };
+    if (lattice == PTRT_D2Q9) return with_lat(Tag<D2Q9>{});
+    if (lattice == PTRT_D3Q19) return with_lat(Tag<D3Q19>{});
+    return PTRT_EINVAL;
+}
+
+inline size_t storage_bytes(int storage)
+{
+    switch (storage) {
+    case PTRT_F64: return 8;
+    case PTRT_F32: return 4;
+    case PTRT_F16:
+    case PTRT_BF16: return 2;
+    default: return 0;
+    }
+}
+
+inline int lattice_q(int lattice)
+{
+    return lattice == PTRT_D2Q9 ? 9 : (lattice == PTRT_D3Q19 ? 19 : 0);
+}
+
+inline bool finite(double v) { return std::isfinite(v); }
+
+// Checks shared by ptrt_create and the batch descriptors; returns a status
+// and fills msg on failure.
+inline int check_params(int lattice, int nx, int ny, int nz, double tau_plus, double Lambda,
+                        const double *force, std::string &msg)
+{
+    if (lattice != PTRT_D2Q9 && lattice != PTRT_D3Q19) {
+        msg = "unknown lattice id " + std::to_string(lattice);
+        return PTRT_EINVAL;
+    }
+    if (nx <= 0 || ny <= 0 || nz <= 0) {
+        msg = "lattice sizes must be positive";
+        return PTRT_EINVAL;
+    }
+    if (lattice == PTRT_D2Q9 && nz != 1) {
+        msg = "D2Q9 needs nz == 1";
+        return PTRT_EINVAL;
+    }
+    if ((double)nx * ny * nz >= 2147483648.0) {
+        msg = "lattice has 2^31 nodes or more";
+        return PTRT_EINVAL;
+    }
+    if (!finite(tau_plus) || !finite(Lambda) || !(tau_plus > 0.5) || !(Lambda > 0.0)) {
+        msg = "need finite tau_plus > 1/2 and Lambda > 0";
+        return PTRT_ETAU;
+    }
+    if (force)
+        for (int a = 0; a < 3; ++a)
+            if (!finite(force[a])) {
+                msg = "force must be finite";
+                return PTRT_ETAU;
+            }
+    return PTRT_OK;
+}
+
+// tau- from Lambda = (tau+ - 1/2)(tau- - 1/2); relaxation constants 1 - 1/tau.
+inline void relaxation(double tau_plus, double Lambda, double &ap, double &am)
+{
+    const double tau_minus = 0.5 + Lambda / (tau_plus - 0.5);
+    ap = 1.0 - 1.0 / tau_plus;
+    am = 1.0 - 1.0 / tau_minus;
+}
+
+} // namespace ptrt

@@ -1,0 +1,578 @@
+// Batched form of libptrt (declared in include/ptrt.h): many independent
+// D2Q9 lattices of different sizes advanced by one launch per step.
+//
+// Device layout: every instance owns Q planes of qs_k elements at element
+// offset off_k of each of the two population buffers, and nx_k * ny_k mask
+// bytes at offset moff_k of one shared mask array (zeros for instances
+// without solids).  A tile table lists (instance, x0, y0) for every
+// tile_x * tile_y tile of every instance; workgroup b handles tiles
+// b, b + G, b + 2G, ... of the table (G = grid size).  Each node runs the
+// same pull() and collide() as the single-lattice kernel, so an instance
+// evolves bit for bit like a single lattice with the same parameters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_common.hpp"
+
+using namespace ptrt;
+
+namespace {
+
+template <class C>
+struct BInst {
+    long long off, qs, moff;
+    int nx, ny;
+    Relax<C> r;
+};
+
+template <class S>
+__global__ void __launch_bounds__(1024)
+k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+             const BInst<typename Codec<S>::compute> *__restrict__ inst,
+             const int4 *__restrict__ tiles, int ntiles)
+{
+    using C = typename Codec<S>::compute;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BInst<C> p = inst[tl.x];
+        const int x = tl.y + threadIdx.x;
+        const int y = tl.z + threadIdx.y;
+        if (x < p.nx && y < p.ny) {
+            const Geom g{p.nx, p.ny, 1, p.qs};
+            const uint8_t *m = mask + p.moff;
+            const unsigned node = (unsigned)y * (unsigned)p.nx + (unsigned)x;
+            if (!m[node]) {
+                const S *s = src + p.off;
+                S *d = dst + p.off;
+                C h[D2Q9::Q];
+                pull<D2Q9, S, true>(s, m, g, x, y, 0, node, h,
+                                    [](const S *q) { return Codec<S>::load(q); });
+                C rho, ux, uy, uz;
+                collide<D2Q9, C>(h, p.r, rho, ux, uy, uz);
+                static_for<D2Q9::Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    Codec<S>::store(d + (long long)i * g.qs + node, h[i]);
+                });
+            }
+        }
+    }
+}
+
+thread_local std::string g_batch_create_error = "no error";
+constexpr int GRAPH_STEPS = 10; // even: a replay returns to the same buffer parity
+constexpr int BLK_X = 64, BLK_Y = 4;
+
+struct HostInst {
+    int nx, ny;
+    double tau_plus, Lambda, g[3], ap, am;
+    bool has_mask;
+    long long off, qs, moff, N;
+};
+
+} // namespace
+
+struct ptrt_batch {
+    int count = 0, storage = PTRT_F32;
+    std::vector<HostInst> inst;
+    long long total_elems = 0, total_nodes = 0, mask_bytes = 0;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t *d_mask = nullptr;
+    void *d_inst = nullptr;
+    int4 *d_tiles = nullptr;
+    int ntiles = 0;
+    int tile_x = 64, tile_y = 4, blocks = 0, xcd_order = 0;
+    double2 *d_partials = nullptr;
+    int max_parts = 0;
+    double *d_red = nullptr;
+    hipStream_t stream = nullptr, capture_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err = "no error";
+};
+
+namespace {
+
+int bfail(ptrt_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, expr)                                                                      \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return bfail((b), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void drop_graphs(ptrt_batch *b)
+{
+    for (auto &g : b->graph)
+        if (g) {
+            hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+bool valid_plan(int tx, int ty)
+{
+    const int n = tx * ty;
+    return tx >= 32 && ty >= 1 && tx % 32 == 0 &&
+           (n == 64 || n == 128 || n == 256 || n == 512 || n == 1024);
+}
+
+int build_tiles(ptrt_batch *b)
+{
+    std::vector<int4> spatial;
+    for (int k = 0; k < b->count; ++k) {
+        const HostInst &h = b->inst[k];
+        for (int y0 = 0; y0 < h.ny; y0 += b->tile_y)
+            for (int x0 = 0; x0 < h.nx; x0 += b->tile_x) spatial.push_back(make_int4(k, x0, y0, 0));
+    }
+    const int n = (int)spatial.size();
+    std::vector<int4> table(n);
+    if (b->xcd_order) {
+        // table[8m + j] = spatial[j * chunk + m]: with round-robin dispatch of
+        // workgroups over the 8 XCDs, die j walks the j-th contiguous chunk.
+        const int chunk = (n + 7) / 8;
+        int pos = 0;
+        std::vector<int4> out;
+        out.reserve(n);
+        for (int m = 0; m < chunk; ++m)
+            for (int j = 0; j < 8; ++j) {
+                const long long src = (long long)j * chunk + m;
+                if (src < n) out.push_back(spatial[src]);
+            }
+        (void)pos;
+        table = out;
+    } else {
+        table = spatial;
+    }
+    if (b->d_tiles) hipFree(b->d_tiles);
+    b->d_tiles = nullptr;
+    BHIPCHK(b, hipMalloc(&b->d_tiles, sizeof(int4) * (size_t)n));
+    BHIPCHK(b, hipMemcpy(b->d_tiles, table.data(), sizeof(int4) * (size_t)n, hipMemcpyHostToDevice));
+    b->ntiles = n;
+    drop_graphs(b);
+    return PTRT_OK;
+}
+
+template <class S>
+void launch_fused(ptrt_batch *b, hipStream_t s)
+{
+    using C = typename Codec<S>::compute;
+    const int grid = b->blocks > 0 ? std::min(b->blocks, b->ntiles) : b->ntiles;
+    hipLaunchKernelGGL((k_batch_step<S>), dim3(grid), dim3(b->tile_x, b->tile_y, 1), 0, s,
+                       (const S *)b->buf[b->cur], (S *)b->buf[b->cur ^ 1], b->d_mask,
+                       (const BInst<C> *)b->d_inst, b->d_tiles, b->ntiles);
+    b->cur ^= 1;
+}
+
+int launch_fused_any(ptrt_batch *b, hipStream_t s)
+{
+    return dispatch(PTRT_D2Q9, b->storage, false, [&](auto, auto st, auto) -> int {
+        using S = typename decltype(st)::type;
+        launch_fused<S>(b, s);
+        return PTRT_OK;
+    });
+}
+
+int capture_graph(ptrt_batch *b, int parity)
+{
+    const int saved = b->cur;
+    b->cur = parity;
+    hipGraph_t g = nullptr;
+    BHIPCHK(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_STEPS; ++k) launch_fused_any(b, b->capture_stream);
+    hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
+    b->cur = saved;
+    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph[parity], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph[parity] = nullptr;
+        return bfail(b, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return PTRT_OK;
+}
+
+Geom inst_geom(const HostInst &h) { return Geom{h.nx, h.ny, 1, h.qs}; }
+
+int check_instance(ptrt_batch *b, int k)
+{
+    if (!b) return PTRT_EINVAL;
+    if (k < 0 || k >= b->count) return bfail(b, PTRT_EINVAL, "instance index out of range");
+    return PTRT_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, ptrt_batch **out)
+{
+    if (!out || !desc || count <= 0) {
+        g_batch_create_error = "need count > 0 and non-NULL desc / out";
+        return PTRT_EINVAL;
+    }
+    *out = nullptr;
+    if (storage_bytes(storage) == 0) {
+        g_batch_create_error = "unknown storage type";
+        return PTRT_EINVAL;
+    }
+    ptrt_batch *b = new (std::nothrow) ptrt_batch();
+    if (!b) return PTRT_ENOMEM;
+    b->count = count;
+    b->storage = storage;
+    b->inst.resize(count);
+    const size_t elem = storage_bytes(storage);
+    std::vector<uint8_t> mask;
+    long long off = 0, moff = 0;
+    for (int k = 0; k < count; ++k) {
+        const ptrt_instance_desc &d = desc[k];
+        std::string msg;
+        int rc = check_params(PTRT_D2Q9, d.nx, d.ny, 1, d.tau_plus, d.Lambda, d.force, msg);
+        if (rc != PTRT_OK) {
+            g_batch_create_error = "instance " + std::to_string(k) + ": " + msg;
+            delete b;
+            return rc;
+        }
+        HostInst &h = b->inst[k];
+        h.nx = d.nx;
+        h.ny = d.ny;
+        h.N = (long long)d.nx * d.ny;
+        h.tau_plus = d.tau_plus;
+        h.Lambda = d.Lambda;
+        for (int a = 0; a < 3; ++a) h.g[a] = d.force ? d.force[a] : 0.0;
+        h.g[2] = 0.0;
+        relaxation(d.tau_plus, d.Lambda, h.ap, h.am);
+        h.has_mask = false;
+        mask.resize((size_t)(moff + h.N), 0);
+        if (d.solid_mask)
+            for (long long n = 0; n < h.N; ++n)
+                if (d.solid_mask[n]) {
+                    mask[(size_t)(moff + n)] = 1;
+                    h.has_mask = true;
+                }
+        // planes padded to 256 bytes so every plane starts on a cache-line boundary
+        const long long align = 256 / (long long)elem;
+        h.qs = ((h.N + align - 1) / align) * align;
+        h.off = off;
+        h.moff = moff;
+        off += 9 * h.qs;
+        moff += h.N;
+        b->total_nodes += h.N;
+    }
+    b->total_elems = off;
+    b->mask_bytes = moff;
+
+    auto cleanup = [&](int code, const std::string &msg) {
+        g_batch_create_error = msg;
+        ptrt_batch_destroy(b);
+        return code;
+    };
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipMalloc(&b->buf[k], (size_t)b->total_elems * elem);
+        if (e != hipSuccess) {
+            b->buf[k] = nullptr;
+            return cleanup(PTRT_ENOMEM, std::string("hipMalloc of populations: ") + hipGetErrorString(e));
+        }
+        if (hipMemset(b->buf[k], 0, (size_t)b->total_elems * elem) != hipSuccess)
+            return cleanup(PTRT_EDEVICE, "hipMemset failed");
+    }
+    if (hipMalloc(&b->d_mask, (size_t)moff) != hipSuccess ||
+        hipMemcpy(b->d_mask, mask.data(), (size_t)moff, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(PTRT_EDEVICE, "mask upload failed");
+    // instance table in the compute type of the storage
+    int rc = dispatch(PTRT_D2Q9, storage, false, [&](auto, auto st, auto) -> int {
+        using S = typename decltype(st)::type;
+        using C = typename Codec<S>::compute;
+        std::vector<BInst<C>> t(count);
+        for (int k = 0; k < count; ++k) {
+            const HostInst &h = b->inst[k];
+            t[k] = BInst<C>{h.off, h.qs, h.moff, h.nx, h.ny,
+                            Relax<C>{(C)h.ap, (C)h.am, (C)h.g[0], (C)h.g[1], (C)0}};
+        }
+        if (hipMalloc(&b->d_inst, sizeof(BInst<C>) * count) != hipSuccess) return PTRT_EDEVICE;
+        if (hipMemcpy(b->d_inst, t.data(), sizeof(BInst<C>) * count, hipMemcpyHostToDevice) != hipSuccess)
+            return PTRT_EDEVICE;
+        return PTRT_OK;
+    });
+    if (rc != PTRT_OK) return cleanup(rc, "instance table upload failed");
+    for (const auto &h : b->inst)
+        b->max_parts = std::max(b->max_parts, ((h.nx + BLK_X - 1) / BLK_X) * ((h.ny + BLK_Y - 1) / BLK_Y));
+    if (hipMalloc(&b->d_partials, sizeof(double2) * (size_t)b->max_parts) != hipSuccess ||
+        hipMalloc(&b->d_red, 2 * sizeof(double) * (size_t)count) != hipSuccess)
+        return cleanup(PTRT_ENOMEM, "reduction buffers");
+    if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(PTRT_EDEVICE, "capture stream");
+    if (build_tiles(b) != PTRT_OK) return cleanup(PTRT_EDEVICE, b->err);
+    for (int k = 0; k < count; ++k) {
+        rc = ptrt_batch_init_equilibrium(b, k, nullptr, nullptr);
+        if (rc != PTRT_OK) return cleanup(rc, b->err);
+    }
+    *out = b;
+    return PTRT_OK;
+}
+
+int ptrt_batch_set_stream(ptrt_batch *b, void *s)
+{
+    if (!b) return PTRT_EINVAL;
+    b->stream = (hipStream_t)s;
+    return PTRT_OK;
+}
+
+int ptrt_batch_init_equilibrium(ptrt_batch *b, int k, const double *rho, const double *u)
+{
+    int rc = check_instance(b, k);
+    if (rc != PTRT_OK) return rc;
+    const HostInst &h = b->inst[k];
+    double *d_in = nullptr;
+    BHIPCHK(b, hipMalloc(&d_in, sizeof(double) * 3 * (size_t)h.N));
+    hipError_t e = hipSuccess;
+    if (rho) e = hipMemcpyAsync(d_in, rho, sizeof(double) * h.N, hipMemcpyHostToDevice, b->stream);
+    if (u && e == hipSuccess)
+        e = hipMemcpyAsync(d_in + h.N, u, sizeof(double) * 2 * h.N, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) {
+        // both buffers hold the same state so that either parity is valid
+        const Geom g = inst_geom(h);
+        for (int k2 = 0; k2 < 2; ++k2) {
+            void *dst = b->buf[b->cur ^ k2];
+            dispatch(PTRT_D2Q9, b->storage, h.has_mask, [&](auto lt, auto st, auto mk) -> int {
+                using L = typename decltype(lt)::type;
+                using S = typename decltype(st)::type;
+                constexpr bool M = decltype(mk)::value;
+                hipLaunchKernelGGL((k_init_eq<L, S, M>), dim3((h.nx + BLK_X - 1) / BLK_X, (h.ny + BLK_Y - 1) / BLK_Y, 1),
+                                   dim3(BLK_X, BLK_Y, 1), 0, b->stream, (S *)dst + h.off, b->d_mask + h.moff, g,
+                                   0, rho ? d_in : nullptr, u ? d_in + h.N : nullptr, h.N);
+                return PTRT_OK;
+            });
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipFree(d_in);
+    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+    return PTRT_OK;
+}
+
+int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int xcd_order)
+{
+    if (!b) return PTRT_EINVAL;
+    if (!valid_plan(tile_x, tile_y) || blocks < 0) return bfail(b, PTRT_EINVAL, "invalid tile plan");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->tile_x = tile_x;
+    b->tile_y = tile_y;
+    b->blocks = blocks;
+    b->xcd_order = xcd_order ? 1 : 0;
+    return build_tiles(b);
+}
+
+int ptrt_batch_step(ptrt_batch *b, int n)
+{
+    if (!b) return PTRT_EINVAL;
+    if (n < 0) return bfail(b, PTRT_EINVAL, "negative step count");
+    while (n >= GRAPH_STEPS) {
+        if (!b->graph[b->cur]) {
+            int rc = capture_graph(b, b->cur);
+            if (rc != PTRT_OK) return rc;
+        }
+        BHIPCHK(b, hipGraphLaunch(b->graph[b->cur], b->stream));
+        n -= GRAPH_STEPS;
+    }
+    for (; n > 0; --n) launch_fused_any(b, b->stream);
+    BHIPCHK(b, hipGetLastError());
+    return PTRT_OK;
+}
+
+int ptrt_batch_step_separate(ptrt_batch *b, int n)
+{
+    if (!b) return PTRT_EINVAL;
+    if (n < 0) return bfail(b, PTRT_EINVAL, "negative step count");
+    for (int s = 0; s < n; ++s) {
+        for (int k = 0; k < b->count; ++k) {
+            const HostInst &h = b->inst[k];
+            const Geom g = inst_geom(h);
+            const int bx = 64, by = 4;
+            const dim3 grid((h.nx + bx - 1) / bx, (h.ny + by - 1) / by, 1);
+            dispatch(PTRT_D2Q9, b->storage, h.has_mask, [&](auto lt, auto st, auto mk) -> int {
+                using L = typename decltype(lt)::type;
+                using S = typename decltype(st)::type;
+                using C = typename Codec<S>::compute;
+                constexpr bool M = decltype(mk)::value;
+                const Relax<C> r{(C)h.ap, (C)h.am, (C)h.g[0], (C)h.g[1], (C)0};
+                hipLaunchKernelGGL((k_step<L, S, M, false>), grid, dim3(bx, by, 1), 0, b->stream,
+                                   (const S *)b->buf[b->cur] + h.off, (S *)b->buf[b->cur ^ 1] + h.off,
+                                   b->d_mask + h.moff, g, r, (double2 *)nullptr);
+                return PTRT_OK;
+            });
+        }
+        b->cur ^= 1;
+    }
+    BHIPCHK(b, hipGetLastError());
+    return PTRT_OK;
+}
+
+int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int *xcd_o)
+{
+    if (!b) return PTRT_EINVAL;
+    static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {32, 8},
+                                    {64, 8}, {256, 1}, {128, 4}, {32, 16}};
+    static const int grids[] = {0, 2048, 4096};
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bt[4] = {b->tile_x, b->tile_y, b->blocks, b->xcd_order};
+    int rc = PTRT_OK;
+    for (const auto &sh : shapes)
+        for (int gsz : grids)
+            for (int xo = 0; xo < 2 && rc == PTRT_OK; ++xo) {
+                rc = ptrt_batch_set_plan(b, sh[0], sh[1], gsz, xo);
+                if (rc != PTRT_OK) break;
+                for (int k = 0; k < 2; ++k) launch_fused_any(b, b->stream);
+                hipEventRecord(e0, b->stream);
+                for (int k = 0; k < 6; ++k) launch_fused_any(b, b->stream);
+                hipEventRecord(e1, b->stream);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = bfail(b, PTRT_EDEVICE, "autotune timing failed");
+                    break;
+                }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    bt[0] = sh[0];
+                    bt[1] = sh[1];
+                    bt[2] = gsz;
+                    bt[3] = xo;
+                }
+            }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != PTRT_OK) return rc;
+    rc = ptrt_batch_set_plan(b, bt[0], bt[1], bt[2], bt[3]);
+    if (tx_o) *tx_o = bt[0];
+    if (ty_o) *ty_o = bt[1];
+    if (blocks_o) *blocks_o = bt[2];
+    if (xcd_o) *xcd_o = bt[3];
+    return rc;
+}
+
+static int batch_download(ptrt_batch *b, int k, double *rho, double *u, double *f)
+{
+    int rc = check_instance(b, k);
+    if (rc != PTRT_OK) return rc;
+    const HostInst &h = b->inst[k];
+    const int per = (rho ? 1 : 0) + (u ? 3 : 0) + (f ? 9 : 0);
+    if (per == 0) return PTRT_OK;
+    double *d_out = nullptr;
+    BHIPCHK(b, hipMalloc(&d_out, sizeof(double) * per * (size_t)h.N));
+    double *d_rho = rho ? d_out : nullptr;
+    double *d_u = u ? d_out + (rho ? h.N : 0) : nullptr;
+    double *d_f = f ? d_out + ((rho ? 1 : 0) + (u ? 3 : 0)) * h.N : nullptr;
+    const Geom g = inst_geom(h);
+    dispatch(PTRT_D2Q9, b->storage, h.has_mask, [&](auto lt, auto st, auto mk) -> int {
+        using L = typename decltype(lt)::type;
+        using S = typename decltype(st)::type;
+        constexpr bool M = decltype(mk)::value;
+        hipLaunchKernelGGL((k_gather<L, S, M>), dim3((h.nx + BLK_X - 1) / BLK_X, (h.ny + BLK_Y - 1) / BLK_Y, 1),
+                           dim3(BLK_X, BLK_Y, 1), 0, b->stream, (const S *)b->buf[b->cur] + h.off,
+                           b->d_mask + h.moff, g, 0, h.g[0], h.g[1], 0.0, d_rho, d_u, d_f, h.N,
+                           (double2 *)nullptr);
+        return PTRT_OK;
+    });
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && rho)
+        e = hipMemcpyAsync(rho, d_rho, sizeof(double) * h.N, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess && u)
+        e = hipMemcpyAsync(u, d_u, sizeof(double) * 2 * h.N, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess && f)
+        e = hipMemcpyAsync(f, d_f, sizeof(double) * 9 * h.N, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipFree(d_out);
+    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("download: ") + hipGetErrorString(e));
+    if (u) std::memset(u + 2 * h.N, 0, sizeof(double) * h.N);
+    return PTRT_OK;
+}
+
+int ptrt_batch_moments(ptrt_batch *b, int k, double *rho, double *u)
+{
+    return batch_download(b, k, rho, u, nullptr);
+}
+
+int ptrt_batch_get_populations(ptrt_batch *b, int k, double *f)
+{
+    if (!f) return bfail(b, PTRT_EINVAL, "NULL argument");
+    return batch_download(b, k, nullptr, nullptr, f);
+}
+
+int ptrt_batch_diagnostics(ptrt_batch *b, double *mass, double *ke)
+{
+    if (!b) return PTRT_EINVAL;
+    for (int k = 0; k < b->count; ++k) {
+        const HostInst &h = b->inst[k];
+        const Geom g = inst_geom(h);
+        const dim3 grid((h.nx + BLK_X - 1) / BLK_X, (h.ny + BLK_Y - 1) / BLK_Y, 1);
+        dispatch(PTRT_D2Q9, b->storage, h.has_mask, [&](auto lt, auto st, auto mk) -> int {
+            using L = typename decltype(lt)::type;
+            using S = typename decltype(st)::type;
+            constexpr bool M = decltype(mk)::value;
+            hipLaunchKernelGGL((k_gather<L, S, M>), grid, dim3(BLK_X, BLK_Y, 1), 0, b->stream,
+                               (const S *)b->buf[b->cur] + h.off, b->d_mask + h.moff, g, 0, h.g[0],
+                               h.g[1], 0.0, (double *)nullptr, (double *)nullptr, (double *)nullptr,
+                               0LL, b->d_partials);
+            return PTRT_OK;
+        });
+        hipLaunchKernelGGL(k_finalize<256>, dim3(1), dim3(256), 0, b->stream, b->d_partials,
+                           (int)(grid.x * grid.y), b->d_red + 2 * k);
+    }
+    BHIPCHK(b, hipGetLastError());
+    std::vector<double> r(2 * (size_t)b->count);
+    BHIPCHK(b, hipMemcpyAsync(r.data(), b->d_red, sizeof(double) * r.size(), hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    bool ok = true;
+    for (int k = 0; k < b->count; ++k) {
+        if (mass) mass[k] = r[2 * k];
+        if (ke) ke[k] = r[2 * k + 1];
+        ok = ok && std::isfinite(r[2 * k]) && std::isfinite(r[2 * k + 1]);
+    }
+    if (!ok) return bfail(b, PTRT_EDIVERGED, "non-finite mass or kinetic energy");
+    return PTRT_OK;
+}
+
+long long ptrt_batch_nodes(const ptrt_batch *b) { return b ? b->total_nodes : 0; }
+
+double ptrt_batch_bytes_per_step(const ptrt_batch *b)
+{
+    if (!b) return 0.0;
+    return (2.0 * 9 * (double)storage_bytes(b->storage) + 1.0) * (double)b->total_nodes;
+}
+
+const char *ptrt_batch_last_error(const ptrt_batch *b)
+{
+    return b ? b->err.c_str() : g_batch_create_error.c_str();
+}
+
+int ptrt_batch_destroy(ptrt_batch *b)
+{
+    if (!b) return PTRT_OK;
+    hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (int k = 0; k < 2; ++k)
+        if (b->buf[k]) hipFree(b->buf[k]);
+    if (b->d_mask) hipFree(b->d_mask);
+    if (b->d_inst) hipFree(b->d_inst);
+    if (b->d_tiles) hipFree(b->d_tiles);
+    if (b->d_partials) hipFree(b->d_partials);
+    if (b->d_red) hipFree(b->d_red);
+    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    delete b;
+    return PTRT_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,431 @@
+// Single-lattice entry points of libptrt (declared in include/ptrt.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_common.hpp"
+
+using namespace ptrt;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr int BLK_X = 64, BLK_Y = 4; // gather / scatter workgroup shape
+
+} // namespace
+
+struct ptrt_ctx {
+    int lattice = 0, Q = 0;
+    int nx = 0, ny = 0, nz = 0;
+    long long N = 0, qs = 0;
+    double tau_plus = 0, Lambda = 0, g[3] = {0, 0, 0};
+    double ap = 0, am = 0;
+    int storage = PTRT_F32;
+    bool has_mask = false;
+    std::vector<uint8_t> h_mask;
+    uint8_t *d_mask = nullptr;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    double2 *d_partials = nullptr;
+    int nparts = 0;
+    double *d_red = nullptr;
+    hipStream_t stream = nullptr;
+    bool allocated = false, initialized = false;
+    long long t = 0;
+    int step_bx = 64, step_by = 4;
+    std::string err = "no error";
+};
+
+namespace {
+
+int fail(ptrt_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((c), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+dim3 gather_grid(const ptrt_ctx *c, int nzs)
+{
+    return dim3((c->nx + BLK_X - 1) / BLK_X, (c->ny + BLK_Y - 1) / BLK_Y, nzs);
+}
+
+// z-slab height so that a [Q][slab] FP64 host transfer stays under ~512 MB
+int slab_planes(const ptrt_ctx *c, int per_node_doubles)
+{
+    const double plane = (double)c->nx * c->ny * per_node_doubles * 8.0;
+    int s = (int)std::max(1.0, 512.0 * 1024 * 1024 / plane);
+    return std::min(s, c->nz);
+}
+
+int ensure_allocated(ptrt_ctx *c)
+{
+    if (c->allocated) return PTRT_OK;
+    const size_t elem = storage_bytes(c->storage);
+    // plane stride: round up to 256 elements plus one 512-byte shift per plane
+    // so that the Q streams do not start on the same HBM channel
+    const long long pad = 512 / (long long)elem;
+    c->qs = ((c->N + 255) / 256) * 256 + pad;
+    const size_t bytes = (size_t)c->Q * (size_t)c->qs * elem;
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipMalloc(&c->buf[k], bytes);
+        if (e != hipSuccess) {
+            c->buf[k] = nullptr;
+            return fail(c, PTRT_ENOMEM, std::string("hipMalloc of populations: ") + hipGetErrorString(e));
+        }
+        HIPCHK(c, hipMemset(c->buf[k], 0, bytes));
+    }
+    if (c->has_mask) {
+        HIPCHK(c, hipMalloc(&c->d_mask, (size_t)c->N));
+        HIPCHK(c, hipMemcpy(c->d_mask, c->h_mask.data(), (size_t)c->N, hipMemcpyHostToDevice));
+    }
+    const dim3 gg = gather_grid(c, c->nz);
+    c->nparts = gg.x * gg.y * gg.z;
+    HIPCHK(c, hipMalloc(&c->d_partials, sizeof(double2) * (size_t)c->nparts));
+    HIPCHK(c, hipMalloc(&c->d_red, 2 * sizeof(double)));
+    c->allocated = true;
+    return PTRT_OK;
+}
+
+Geom geom(const ptrt_ctx *c) { return Geom{c->nx, c->ny, c->nz, c->qs}; }
+
+// Scatter host data (equilibrium from rho/u, or populations f) into the
+// current buffer, slab by slab.
+int upload_state(ptrt_ctx *c, const double *rho, const double *u, const double *f)
+{
+    const bool pops = f != nullptr;
+    const int per_node = pops ? c->Q : 4;
+    const int slab = slab_planes(c, per_node);
+    const long long plane = (long long)c->nx * c->ny;
+    double *d_in = nullptr;
+    const size_t in_elems = (size_t)per_node * slab * plane;
+    HIPCHK(c, hipMalloc(&d_in, in_elems * sizeof(double)));
+    int rc = PTRT_OK;
+    for (int z0 = 0; z0 < c->nz && rc == PTRT_OK; z0 += slab) {
+        const int nzs = std::min(slab, c->nz - z0);
+        const long long cnt = nzs * plane;
+        const double *d_rho = nullptr, *d_u = nullptr;
+        hipError_t e = hipSuccess;
+        if (pops) {
+            for (int i = 0; i < c->Q && e == hipSuccess; ++i)
+                e = hipMemcpyAsync(d_in + (size_t)i * cnt, f + (size_t)i * c->N + z0 * plane,
+                                   cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        } else {
+            if (rho) {
+                e = hipMemcpyAsync(d_in, rho + z0 * plane, cnt * sizeof(double),
+                                   hipMemcpyHostToDevice, c->stream);
+                d_rho = d_in;
+            }
+            if (u && e == hipSuccess) {
+                const int D = c->lattice == PTRT_D2Q9 ? 2 : 3;
+                for (int a = 0; a < D && e == hipSuccess; ++a)
+                    e = hipMemcpyAsync(d_in + (size_t)(1 + a) * cnt, u + (size_t)a * c->N + z0 * plane,
+                                       cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
+                d_u = d_in + cnt;
+            }
+        }
+        if (e != hipSuccess) {
+            rc = fail(c, PTRT_EDEVICE, std::string("host to device copy: ") + hipGetErrorString(e));
+            break;
+        }
+        const Geom g = geom(c);
+        void *dst = c->buf[c->cur];
+        const dim3 grid = gather_grid(c, nzs), block(BLK_X, BLK_Y, 1);
+        dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
+            using L = typename decltype(lt)::type;
+            using S = typename decltype(st)::type;
+            constexpr bool M = decltype(mk)::value;
+            if (pops)
+                hipLaunchKernelGGL((k_set_state<L, S, M>), grid, block, 0, c->stream, (S *)dst,
+                                   c->d_mask, g, z0, d_in, cnt);
+            else
+                hipLaunchKernelGGL((k_init_eq<L, S, M>), grid, block, 0, c->stream, (S *)dst,
+                                   c->d_mask, g, z0, d_rho, d_u, cnt);
+            return PTRT_OK;
+        });
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = fail(c, PTRT_EDEVICE, std::string("state upload: ") + hipGetErrorString(e));
+    }
+    hipFree(d_in);
+    return rc;
+}
+
+// Gather rho/u/f (any may be null) of the state at t to host arrays.
+int download_state(ptrt_ctx *c, double *rho, double *u, double *f)
+{
+    const int per_node = (f ? c->Q : 0) + (rho ? 1 : 0) + (u ? 3 : 0);
+    if (per_node == 0) return PTRT_OK;
+    const int slab = slab_planes(c, per_node);
+    const long long plane = (long long)c->nx * c->ny;
+    double *d_out = nullptr;
+    HIPCHK(c, hipMalloc(&d_out, (size_t)per_node * slab * plane * sizeof(double)));
+    int rc = PTRT_OK;
+    for (int z0 = 0; z0 < c->nz; z0 += slab) {
+        const int nzs = std::min(slab, c->nz - z0);
+        const long long cnt = nzs * plane;
+        double *d_rho = rho ? d_out : nullptr;
+        double *d_u = u ? d_out + (rho ? cnt : 0) : nullptr;
+        double *d_f = f ? d_out + ((rho ? 1 : 0) + (u ? 3 : 0)) * cnt : nullptr;
+        const Geom g = geom(c);
+        const void *src = c->buf[c->cur];
+        const dim3 grid = gather_grid(c, nzs), block(BLK_X, BLK_Y, 1);
+        dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
+            using L = typename decltype(lt)::type;
+            using S = typename decltype(st)::type;
+            constexpr bool M = decltype(mk)::value;
+            hipLaunchKernelGGL((k_gather<L, S, M>), grid, block, 0, c->stream, (const S *)src,
+                               c->d_mask, g, z0, c->g[0], c->g[1], c->g[2], d_rho, d_u, d_f, cnt,
+                               (double2 *)nullptr);
+            return PTRT_OK;
+        });
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && rho)
+            e = hipMemcpyAsync(rho + z0 * plane, d_rho, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (u) {
+            const int D = c->lattice == PTRT_D2Q9 ? 2 : 3;
+            for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+                if (a < D)
+                    e = hipMemcpyAsync(u + (size_t)a * c->N + z0 * plane, d_u + (size_t)a * cnt,
+                                       cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            }
+        }
+        if (f)
+            for (int i = 0; i < c->Q && e == hipSuccess; ++i)
+                e = hipMemcpyAsync(f + (size_t)i * c->N + z0 * plane, d_f + (size_t)i * cnt,
+                                   cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            rc = fail(c, PTRT_EDEVICE, std::string("state download: ") + hipGetErrorString(e));
+            break;
+        }
+    }
+    if (u && c->lattice == PTRT_D2Q9) std::memset(u + 2 * (size_t)c->N, 0, (size_t)c->N * sizeof(double));
+    hipFree(d_out);
+    return rc;
+}
+
+} // namespace
+
+extern "C" {
+
+int ptrt_create(int lattice, int nx, int ny, int nz, double tau_plus, double Lambda,
+                const double *force, const uint8_t *solid_mask, ptrt_ctx **out)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return PTRT_EINVAL;
+    }
+    *out = nullptr;
+    std::string msg;
+    int rc = check_params(lattice, nx, ny, nz, tau_plus, Lambda, force, msg);
+    if (rc != PTRT_OK) {
+        g_create_error = msg;
+        return rc;
+    }
+    ptrt_ctx *c = new (std::nothrow) ptrt_ctx();
+    if (!c) {
+        g_create_error = "out of host memory";
+        return PTRT_ENOMEM;
+    }
+    c->lattice = lattice;
+    c->Q = lattice_q(lattice);
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->N = (long long)nx * ny * nz;
+    c->tau_plus = tau_plus;
+    c->Lambda = Lambda;
+    if (force)
+        for (int a = 0; a < 3; ++a) c->g[a] = force[a];
+    if (lattice == PTRT_D2Q9) c->g[2] = 0.0;
+    relaxation(tau_plus, Lambda, c->ap, c->am);
+    if (solid_mask) {
+        c->h_mask.assign(solid_mask, solid_mask + c->N);
+        for (auto &v : c->h_mask) v = v ? 1 : 0;
+        c->has_mask = std::any_of(c->h_mask.begin(), c->h_mask.end(), [](uint8_t v) { return v; });
+        if (!c->has_mask) c->h_mask.clear();
+    }
+    if (nx >= 256 && nx % 256 == 0) {
+        c->step_bx = 256;
+        c->step_by = 1;
+    } else if (nx >= 128 && nx % 128 == 0) {
+        c->step_bx = 128;
+        c->step_by = 2;
+    }
+    *out = c;
+    return PTRT_OK;
+}
+
+int ptrt_set_storage(ptrt_ctx *c, int storage)
+{
+    if (!c) return PTRT_EINVAL;
+    if (storage_bytes(storage) == 0) return fail(c, PTRT_EINVAL, "unknown storage type");
+    if (c->allocated) return fail(c, PTRT_ESTATE, "storage can only change before the first init");
+    c->storage = storage;
+    return PTRT_OK;
+}
+
+int ptrt_set_stream(ptrt_ctx *c, void *s)
+{
+    if (!c) return PTRT_EINVAL;
+    c->stream = (hipStream_t)s;
+    return PTRT_OK;
+}
+
+int ptrt_init_equilibrium(ptrt_ctx *c, const double *rho, const double *u)
+{
+    if (!c) return PTRT_EINVAL;
+    int rc = ensure_allocated(c);
+    if (rc != PTRT_OK) return rc;
+    rc = upload_state(c, rho, u, nullptr);
+    if (rc != PTRT_OK) return rc;
+    c->initialized = true;
+    c->t = 0;
+    return PTRT_OK;
+}
+
+int ptrt_set_populations(ptrt_ctx *c, const double *f)
+{
+    if (!c || !f) return fail(c, PTRT_EINVAL, "NULL argument");
+    int rc = ensure_allocated(c);
+    if (rc != PTRT_OK) return rc;
+    rc = upload_state(c, nullptr, nullptr, f);
+    if (rc != PTRT_OK) return rc;
+    c->initialized = true;
+    return PTRT_OK;
+}
+
+int ptrt_step(ptrt_ctx *c, int n)
+{
+    if (!c) return PTRT_EINVAL;
+    if (n < 0) return fail(c, PTRT_EINVAL, "negative step count");
+    if (!c->initialized) return fail(c, PTRT_ESTATE, "ptrt_step before init");
+    const Geom g = geom(c);
+    const dim3 block(c->step_bx, c->step_by, 1);
+    const dim3 grid((c->nx + c->step_bx - 1) / c->step_bx, (c->ny + c->step_by - 1) / c->step_by, c->nz);
+    for (int k = 0; k < n; ++k) {
+        const void *src = c->buf[c->cur];
+        void *dst = c->buf[c->cur ^ 1];
+        dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
+            using L = typename decltype(lt)::type;
+            using S = typename decltype(st)::type;
+            using C = typename Codec<S>::compute;
+            constexpr bool M = decltype(mk)::value;
+            const Relax<C> r{(C)c->ap, (C)c->am, (C)c->g[0], (C)c->g[1], (C)c->g[2]};
+            hipLaunchKernelGGL((k_step<L, S, M, false>), grid, block, 0, c->stream, (const S *)src,
+                               (S *)dst, c->d_mask, g, r, (double2 *)nullptr);
+            return PTRT_OK;
+        });
+        c->cur ^= 1;
+    }
+    c->t += n;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return PTRT_OK;
+}
+
+int ptrt_moments(ptrt_ctx *c, double *rho_out, double *u_out)
+{
+    if (!c) return PTRT_EINVAL;
+    if (!c->initialized) return fail(c, PTRT_ESTATE, "moments before init");
+    return download_state(c, rho_out, u_out, nullptr);
+}
+
+int ptrt_get_populations(ptrt_ctx *c, double *f_out)
+{
+    if (!c || !f_out) return fail(c, PTRT_EINVAL, "NULL argument");
+    if (!c->initialized) return fail(c, PTRT_ESTATE, "get_populations before init");
+    return download_state(c, nullptr, nullptr, f_out);
+}
+
+int ptrt_diagnostics(ptrt_ctx *c, double *mass, double *ke)
+{
+    if (!c) return PTRT_EINVAL;
+    if (!c->initialized) return fail(c, PTRT_ESTATE, "diagnostics before init");
+    const Geom g = geom(c);
+    const void *src = c->buf[c->cur];
+    const dim3 grid = gather_grid(c, c->nz), block(BLK_X, BLK_Y, 1);
+    dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
+        using L = typename decltype(lt)::type;
+        using S = typename decltype(st)::type;
+        constexpr bool M = decltype(mk)::value;
+        hipLaunchKernelGGL((k_gather<L, S, M>), grid, block, 0, c->stream, (const S *)src, c->d_mask,
+                           g, 0, c->g[0], c->g[1], c->g[2], (double *)nullptr, (double *)nullptr,
+                           (double *)nullptr, 0LL, c->d_partials);
+        return PTRT_OK;
+    });
+    hipLaunchKernelGGL(k_finalize<256>, dim3(1), dim3(256), 0, c->stream, c->d_partials, c->nparts, c->d_red);
+    HIPCHK(c, hipGetLastError());
+    double r[2];
+    HIPCHK(c, hipMemcpyAsync(r, c->d_red, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (mass) *mass = r[0];
+    if (ke) *ke = r[1];
+    if (!std::isfinite(r[0]) || !std::isfinite(r[1]))
+        return fail(c, PTRT_EDIVERGED, "non-finite mass or kinetic energy at step " + std::to_string(c->t));
+    return PTRT_OK;
+}
+
+int ptrt_get_time(const ptrt_ctx *c, long long *t)
+{
+    if (!c || !t) return PTRT_EINVAL;
+    *t = c->t;
+    return PTRT_OK;
+}
+
+const char *ptrt_last_error(const ptrt_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int ptrt_destroy(ptrt_ctx *c)
+{
+    if (!c) return PTRT_OK;
+    hipError_t e = hipSuccess;
+    if (c->allocated) e = hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k)
+        if (c->buf[k]) hipFree(c->buf[k]);
+    if (c->d_mask) hipFree(c->d_mask);
+    if (c->d_partials) hipFree(c->d_partials);
+    if (c->d_red) hipFree(c->d_red);
+    delete c;
+    return e == hipSuccess ? PTRT_OK : PTRT_EDEVICE;
+}
+
+int ptrt_velocity_set(int lattice, int *e_out, double *w_out)
+{
+    auto fill = [&](auto lt) {
+        using L = typename decltype(lt)::type;
+        for (int i = 0; i < L::Q; ++i) {
+            if (e_out) {
+                e_out[3 * i] = L::ex(i);
+                e_out[3 * i + 1] = L::ey(i);
+                e_out[3 * i + 2] = L::ez(i);
+            }
+            if (w_out) w_out[i] = L::w(i);
+        }
+        return L::Q;
+    };
+    if (lattice == PTRT_D2Q9) return fill(Tag<D2Q9>{});
+    if (lattice == PTRT_D3Q19) return fill(Tag<D3Q19>{});
+    return PTRT_EINVAL;
+}
+
+double ptrt_bytes_per_node(const ptrt_ctx *c)
+{
+    if (!c) return 0.0;
+    return 2.0 * c->Q * (double)storage_bytes(c->storage) + (c->has_mask ? 1.0 : 0.0);
+}
+
+} // extern "C"

@@ -1,0 +1,90 @@
+"""The C interface without a GPU: the library loads, exports every entry point
+that include/ptrt.h declares, reports the documented velocity tables and
+rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import ptrt as O
+
+P = pytest.importorskip("paper_2602_06686_amd.ptrt")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ptrt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptrt_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = ctypes.CDLL(P.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 28
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTED) == declared
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_velocity_tables_match_oracle(lat):
+    e, w = P.ptrt_velocity_set(lat)
+    eo, wo, _ = O.lattice(lat)
+    assert (e == eo).all()
+    assert np.abs(w - wo).max() < 1e-16
+
+
+def test_velocity_set_rejects_unknown_lattice():
+    assert P._lib.ptrt_velocity_set(7, None, None) == -1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((2, 8, 8, 1, 0.6, 0.25), -1),        # unknown lattice
+    ((0, 8, 8, 2, 0.6, 0.25), -1),        # D2Q9 with nz != 1
+    ((1, 0, 8, 8, 0.6, 0.25), -1),        # empty lattice
+    ((1, 2048, 2048, 1024, 0.6, 0.25), -1),  # 2^32 nodes
+    ((0, 8, 8, 1, 0.5, 0.25), -2),        # tau+ = 1/2
+    ((0, 8, 8, 1, 0.7, 0.0), -2),         # Lambda = 0
+    ((0, 8, 8, 1, float("nan"), 0.25), -2),
+])
+def test_create_validation(args, code):
+    with pytest.raises(P.PtrtError) as ei:
+        P.ptrt_create(*args)
+    assert ei.value.code == code
+    assert P.ptrt_last_error() != "no error"
+
+
+def test_nonfinite_force_rejected():
+    with pytest.raises(P.PtrtError) as ei:
+        P.ptrt_create(0, 8, 8, 1, 0.7, 0.25, force=[float("inf"), 0, 0])
+    assert ei.value.code == -2
+
+
+def test_state_errors_without_device():
+    h = P.ptrt_create(1, 4, 5, 6, 0.7, 0.25)
+    try:
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_step(h, 1)
+        assert ei.value.code == -6               # step before init
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_step(h, -1)
+        assert ei.value.code == -1
+        with pytest.raises(P.PtrtError):
+            P.ptrt_set_storage(h, 9)
+        assert P.ptrt_get_time(h) == 0
+        assert P.ptrt_bytes_per_node(h) == 2 * 19 * 4
+    finally:
+        P.ptrt_destroy(h)
+    assert P._lib.ptrt_destroy(None) == 0
+
+
+def test_batch_create_validation():
+    with pytest.raises(P.PtrtError) as ei:
+        P.ptrt_batch_create([{"nx": 8, "ny": 8, "tau_plus": 0.4, "Lambda": 0.25}])
+    assert ei.value.code == -2
+    assert "instance 0" in P.ptrt_batch_last_error()
+    with pytest.raises(P.PtrtError):
+        P.ptrt_batch_create([])
