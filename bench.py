@@ -1,0 +1,278 @@
+"""Throughput of the P-TRT hot path on one MI355X.
+
+Headline (``value``): MLUPS of the fused D3Q19 FP32 step on the 256^3
+triply periodic Taylor-Green vortex (U0 = 0.05, Re = 1600, Lambda = 1/4),
+inputs resident in HBM, timed with HIP events on the stream the kernels run
+on.  The same JSON line carries the other forms of the metric:
+D3Q19 512^3 with FP32 vs FP16 vs BF16 shifted storage, the batched D2Q9
+form (512 uneven lattices, one graph-replayed launch per step, and the
+one-launch-per-lattice comparison), and the two D2Q9 single-lattice
+configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64).
+
+``roofline`` describes the dominant kernel (the D3Q19 FP32 step): the
+algorithmic bytes per launch (2 * 19 * 4 bytes per node) over the average
+launch time, against the 8 TB/s HBM peak.  ``traffic`` is read from the
+committed rocprofv3 counter summary when it was taken on the current kernel
+sources, else null.  ``cpu_baseline`` times the FP64 C oracle on two steps of
+the same 256^3 lattice on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only FORM]
+                       [--no-cpu] [--copy-calibration]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d3q19_f32_256_traffic.json")
+KERNEL_SOURCES = ["paper_2602_06686_amd/csrc/kernels.hpp", "paper_2602_06686_amd/csrc/collide.hpp",
+                  "paper_2602_06686_amd/csrc/codec.hpp", "paper_2602_06686_amd/csrc/lattice.hpp",
+                  "paper_2602_06686_amd/csrc/ptrt_single.hip"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(torch, stream, step_fn, steps, warmup):
+    """Run warmup steps, then time exactly `steps` steps with HIP events on
+    `stream` (bracketed by device synchronisation).  Returns (event ms, wall s)."""
+    if warmup:
+        step_fn(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    step_fn(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), wall
+
+
+def bench_single(P, torch, stream, lattice, shape, storage, init, tau_plus, Lambda, steps, warmup,
+                 force=None, mask=None, diag=False):
+    nz, ny, nx = shape
+    with P.Lattice(lattice, nx, ny, nz, tau_plus, Lambda, force=force, solid_mask=mask,
+                   storage=storage, stream=stream) as L:
+        rho, u = init()
+        L.init_equilibrium(rho, u)
+        del rho, u
+        e0 = None
+        if diag:
+            m0, e0 = L.diagnostics(raise_on_divergence=False)
+        ms, wall = timed_steps(torch, stream, L.step, steps, warmup)
+        nodes = nx * ny * nz
+        res = {
+            "shape": [nx, ny, nz], "storage": storage, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms / steps, "mlups": nodes * steps / (ms * 1e-3) / 1e6,
+            "wall_mlups": nodes * steps / wall / 1e6,
+            "bytes_per_node": L.bytes_per_node,
+        }
+        res["achieved_gbs"] = res["bytes_per_node"] * nodes / (res["ms_per_step"] * 1e-3) / 1e9
+        res["hbm_frac"] = res["achieved_gbs"] / HBM_PEAK_GBS
+        if diag:
+            m1, e1 = L.diagnostics(raise_on_divergence=False)
+            res["mass_rel_change"] = abs(m1 - m0) / m0
+            res["kinetic_energy_ratio"] = e1 / e0 if e0 else None
+            res["steps_total"] = L.t
+    return res
+
+
+def form_d3q19(P, torch, stream, n, storage, steps, warmup, diag=False):
+    import lbm_inputs as I
+    prm = I.tgv3d_params(n)
+    r = bench_single(P, torch, stream, P.PTRT_D3Q19, (n, n, n), storage,
+                     lambda: I.tgv3d(n, 0.05), prm["tau_plus"], 0.25, steps, warmup, diag=diag)
+    r["workload"] = f"D3Q19 P-TRT {storage.upper()} {n}^3 periodic 3D Taylor-Green vortex (U0=0.05, Re=1600, Lambda=1/4)"
+    return r
+
+
+def form_dsl(P, torch, stream, steps, warmup):
+    import lbm_inputs as I
+    n, U0, Re = 2048, 0.05, 1e4
+    tp = I.tau_plus_from_nu(U0 * n / Re)
+    r = bench_single(P, torch, stream, P.PTRT_D2Q9, (1, n, n), "f32",
+                     lambda: I.double_shear_layer(n, U0), tp, 0.25, steps, warmup)
+    r["workload"] = "D2Q9 P-TRT FP32 2048^2 doubly periodic double shear layer (kappa=80, delta=0.05, U0=0.05, Re=1e4, Lambda=1/4)"
+    r["note"] = "302 MB working set, partly resident in the 256 MB Infinity Cache: no HBM roofline claim"
+    return r
+
+
+def form_tgv64(P, torch, stream, steps, warmup):
+    import lbm_inputs as I
+    n = 64
+    r = bench_single(P, torch, stream, P.PTRT_D2Q9, (1, n, n), "f64",
+                     lambda: I.tgv2d(n, 0.05), I.tau_plus_from_nu(0.01), 0.25, steps, warmup)
+    r["workload"] = "D2Q9 P-TRT FP64 64^2 Taylor-Green vortex (u0=0.05, nu=0.01, Lambda=1/4); launch-bound"
+    return r
+
+
+def form_batch(P, torch, stream, steps, warmup):
+    import lbm_inputs as I
+    specs = I.batch_specs()
+    b = P.ptrt_batch_create(specs, "f32")
+    try:
+        P.ptrt_batch_set_stream(b, stream)
+        plan = P.ptrt_batch_autotune(b)
+        nodes = P.ptrt_batch_nodes(b)
+        bps = P.ptrt_batch_bytes_per_step(b)
+        ms_f, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step(b, k), steps, warmup)
+        sep_steps = max(10, steps // 10)
+        ms_s, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step_separate(b, k),
+                              sep_steps, 2)
+        fluid = nodes - sum(int(s["mask"].sum()) for s in specs)
+    finally:
+        P.ptrt_batch_destroy(b)
+    mf = ms_f / steps
+    return {
+        "workload": "512 independent D2Q9 P-TRT FP32 lattices (nx, ny in [32, 512], seed 260206686): "
+                    "256 force-driven channels + 256 periodic boxes with a square obstacle, per-instance tau+, Lambda=3/16",
+        "instances": len(specs), "nodes": nodes, "fluid_nodes": fluid,
+        "plan": {"tile_x": plan[0], "tile_y": plan[1], "blocks": plan[2], "xcd_order": plan[3]},
+        "steps": steps, "ms_per_step": mf,
+        "mlups": nodes / (mf * 1e-3) / 1e6, "mflups": fluid / (mf * 1e-3) / 1e6,
+        "achieved_gbs": bps / (mf * 1e-3) / 1e9, "hbm_frac": bps / (mf * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "separate_launches": {"steps": sep_steps, "ms_per_step": ms_s / sep_steps,
+                              "mlups": nodes / (ms_s / sep_steps * 1e-3) / 1e6},
+        "speedup_vs_separate": (ms_s / sep_steps) / mf,
+    }
+
+
+def cpu_baseline(n=256, steps=2):
+    """The FP64 C oracle, as it is, on `steps` steps of the headline lattice."""
+    import lbm_inputs as I
+    from oracle import ptrt as O
+    prm = I.tgv3d_params(n)
+    rho, u = I.tgv3d(n, 0.05)
+    L = O.Lattice(O.D3Q19, n, n, n, prm["tau_plus"], 0.25)
+    L.init_equilibrium(rho, u)
+    del rho, u
+    t0 = time.perf_counter()
+    L.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same {n}^3 D3Q19 lattice (FP64 C oracle, OpenMP over nodes), {dt:.1f} s"}
+
+
+def copy_calibration(torch, stream, nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}
+
+
+def traffic_from_profile():
+    """Per-launch HBM bytes of the headline kernel from the committed counter
+    summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None, "no counter summary"
+    with open(PROFILE_TRAFFIC) as fh:
+        prof = json.load(fh)
+    if prof.get("kernel_source_hash") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return prof.get("bytes_per_launch"), "rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a device copy"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--only", default=None,
+                    help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, tgv64")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_06686_amd import ptrt as P
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    K, W = args.steps, args.warmup
+    only = args.only
+
+    if args.copy_calibration:
+        log("copy calibration", copy_calibration(torch, stream))
+
+    forms = {}
+    head = None
+    if only in (None, "d3q19_256_f32"):
+        log("D3Q19 FP32 256^3")
+        head = form_d3q19(P, torch, stream, 256, "f32", K, W, diag=True)
+        log(json.dumps(head))
+    if only in (None, "d3q19_512"):
+        for st in ("f32", "f16", "bf16"):
+            log(f"D3Q19 {st} 512^3")
+            forms[f"d3q19_512_{st}"] = form_d3q19(P, torch, stream, 512, st, max(20, K // 2), max(2, W // 2))
+            log(json.dumps(forms[f"d3q19_512_{st}"]))
+        f32 = forms["d3q19_512_f32"]["mlups"]
+        forms["fp16_over_fp32_512"] = forms["d3q19_512_f16"]["mlups"] / f32
+        forms["bf16_over_fp32_512"] = forms["d3q19_512_bf16"]["mlups"] / f32
+    if only in (None, "batch"):
+        log("batched D2Q9")
+        forms["batched_d2q9"] = form_batch(P, torch, stream, K, W)
+        log(json.dumps(forms["batched_d2q9"]))
+    if only in (None, "dsl2048"):
+        log("D2Q9 FP32 2048^2")
+        forms["d2q9_2048_f32"] = form_dsl(P, torch, stream, K, W)
+    if only in (None, "tgv64"):
+        log("D2Q9 FP64 64^2")
+        forms["d2q9_64_f64"] = form_tgv64(P, torch, stream, 1000, 50)
+
+    if head is None:
+        print(json.dumps({"forms": forms}))
+        return
+
+    traffic, traffic_note = traffic_from_profile()
+    n_nodes = 256 ** 3
+    roof = {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_step<D3Q19, float, MASK=false>",
+            "bytes_per_launch": head["bytes_per_node"] * n_nodes,
+            "avg_launch_ms": head["ms_per_step"], "traffic_source": traffic_note}
+    cpu = None
+    if not args.no_cpu:
+        log("CPU baseline (oracle)")
+        cpu = cpu_baseline()
+        log(json.dumps(cpu))
+    line = {
+        "metric": "MLUPS & % HBM roofline: D3Q19 P-TRT FP32 vs FP16-storage; batched D2Q9 MLUPS",
+        "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": head["workload"], "lattice": "D3Q19", "nodes": n_nodes,
+                   "storage": "f32", "layout": "SoA two-buffer pull", "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "forms": forms,
+        "headline_detail": head,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
