@@ -190,8 +190,10 @@ int ptrt_batch_init_equilibrium(ptrt_batch *b, int instance, const double *rho,
 int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int xcd_order);
 
 /* Time the candidate plans on the device and keep the fastest; writes the
- * chosen plan if the pointers are not NULL.  Runs (and so advances the batch
- * by) a few steps per candidate.  Synchronous. */
+ * chosen plan if the pointers are not NULL.  The trial steps run on the
+ * current state, which is saved beforehand and restored afterwards, so the
+ * batch is left as it was.  Needs one extra state-sized device buffer for
+ * the duration of the call.  Synchronous. */
 int ptrt_batch_autotune(ptrt_batch *b, int *tile_x, int *tile_y, int *blocks, int *xcd_order);
 
 /* Enqueue n steps, each one launch over every instance, replayed from a

@@ -20,7 +20,11 @@ struct Codec<double> {
     static constexpr int bytes = 8;
     __device__ __forceinline__ static double load(const double *p) { return *p; }
     __device__ __forceinline__ static double to_double(double v) { return v; }
-    __device__ __forceinline__ static void store(double *p, double v) { *p = v; }
+    template <bool NT = false>
+    __device__ __forceinline__ static void store(double *p, double v)
+    {
+        if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+    }
 };
 
 template <>
@@ -28,7 +32,11 @@ struct Codec<float> {
     using compute = float;
     static constexpr int bytes = 4;
     __device__ __forceinline__ static float load(const float *p) { return *p; }
-    __device__ __forceinline__ static void store(float *p, float v) { *p = v; }
+    template <bool NT = false>
+    __device__ __forceinline__ static void store(float *p, float v)
+    {
+        if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+    }
 };
 
 template <>
@@ -36,7 +44,12 @@ struct Codec<_Float16> {
     using compute = float;
     static constexpr int bytes = 2;
     __device__ __forceinline__ static float load(const _Float16 *p) { return (float)*p; }
-    __device__ __forceinline__ static void store(_Float16 *p, float v) { *p = (_Float16)v; }
+    template <bool NT = false>
+    __device__ __forceinline__ static void store(_Float16 *p, float v)
+    {
+        const _Float16 hv = (_Float16)v;
+        if constexpr (NT) __builtin_nontemporal_store(hv, p); else *p = hv;
+    }
 };
 
 template <>
@@ -54,7 +67,12 @@ struct Codec<bf16_t> {
         u += 0x7fffu + ((u >> 16) & 1u);
         return (uint16_t)(u >> 16);
     }
-    __device__ __forceinline__ static void store(bf16_t *p, float v) { p->bits = encode(v); }
+    template <bool NT = false>
+    __device__ __forceinline__ static void store(bf16_t *p, float v)
+    {
+        const uint16_t b = encode(v);
+        if constexpr (NT) __builtin_nontemporal_store(b, &p->bits); else p->bits = b;
+    }
 };
 
 // FP64 read of a stored value (gathers and diagnostics report in FP64).
@@ -72,7 +90,7 @@ __device__ __forceinline__ void store_f64(S *p, double v)
     if constexpr (sizeof(S) >= 4)
         *p = (S)v;
     else
-        Codec<S>::store(p, (float)v);
+        Codec<S>::template store<false>(p, (float)v);
 }
 
 } // namespace ptrt

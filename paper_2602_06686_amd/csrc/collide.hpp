@@ -1,32 +1,44 @@
 // Per-node P-TRT collision (arXiv 2602.06686, Eq. PTRT) on shifted
 // populations h_i = f_i - w_i held in registers.
 //
-// Arithmetic, per node:
-//   drho = sum h_i, rho = 1 + drho, j = sum e_i h_i             (Eq. macro)
-//   F = rho g, u = (j + F/2) / rho
-//   equilibrium (Eq. feq) split by parity: with eu = e_i.u and uu = |u|^2,
+// What is computed, per node (the paper's steps):
+//   drho = sum h_i, rho = 1 + drho, j = sum e_i h_i, F = rho g,
+//   u = (j + F/2) / rho = j / rho + g/2                           (Eq. macro)
+//   f^eq from Eq. feq; with eu = e_i.u and uu = |u|^2 its parity halves are
 //     heq+_i = w_i (drho + rho (9/2 eu^2 - 3/2 uu))
 //     heq-_i = w_i rho eu (3 + 9/2 (eu^2 - uu))
-//   (the third-order Hermite term reduces to (9/2) eu (eu^2 - uu) on lattices
-//   whose velocity components are 0 or +-1)
-//   per inversion pair: neq+ = (h_i + h_ibar)/2 - heq+, neq- = (h_i - h_ibar)/2 - heq-
-//                                                                  (Eq. fneq_parity)
-//   ghost projection P_G from the pair sums (Theorem 2, Eq. ghost_proj)
-//   R2 = neq+ - P_G, R3 = neq- + (3/2) w_i e_i.F                  (Eq. R3_force)
+//   (the third-order Hermite term is (9/2) eu (eu^2 - uu) on lattices whose
+//   velocity components are 0 or +-1)
+//   neq+-_i = (h_i +- h_ibar)/2 - heq+-_i                      (Eq. fneq_parity)
+//   R2 = neq+ - P_G neq,  R3 = neq- + (3/2) w_i e_i.F   (Theorem 2, Eq. R3_force)
 //   h*_i = heq_i + (1 - 1/tau+) R2 + (1 - 1/tau-) R3 + (3/2) w_i e_i.F
 // The last term is the net force source (1/2) w_i e_i.F / c_s^2: the
-// first-order part of f^neq is relaxed with tau+ as in TRT-RLB (sentence
-// after Eq. TRT-RLB) and Scheme II adds (1 - 1/(2 tau+)) w_i e_i.F / c_s^2.
+// first-order part of f^neq relaxes with tau+ as in TRT-RLB (sentence after
+// Eq. TRT-RLB) and Scheme II adds (1 - 1/(2 tau+)) w_i e_i.F / c_s^2.
+//
+// How it is evaluated (same values, fewer operations):
+// * per inversion pair p = (i, ibar): s = h_i + h_ibar, d = h_i - h_ibar;
+//   the moments come from s and d;
+// * the ghost moments are taken from the populations themselves: f^eq and
+//   the shift w_i lie in the span of w_i times Hermite polynomials of order
+//   <= 3, which is orthogonal to every ghost mode (ghosts are symmetric and
+//   weighted-orthogonal to the mass and stress modes), so
+//   sum_j G_j neq_j = sum_j G_j h_j;
+// * with a+ = 1 - 1/tau+, a- = 1 - 1/tau-, sym = (h*_i + h*_ibar)/2 and
+//   anti = (h*_i - h*_ibar)/2:
+//     sym  = (1 - a+) heq+ + a+ (s/2 - P_G)
+//     anti = (1 - a-) heq- + a- d/2 + (1 + a-) (3/2) w_i rho e_i.g
+//   and h*_i = sym + anti, h*_ibar = sym - anti.
 //
 // Ghost projections, derived once from Eq. ghost_proj with an orthogonal
 // basis of the ghost subspace (the subspace the paper's fourth-order
 // products span once their mass and stress components are removed):
-//   D2Q9 (App. A.1): S = (n_0 - 2 sum_axial n + 4 sum_diag n) / 9,
+//   D2Q9 (App. A.1): S = (h_0 - 2 (s_x + s_y) + 4 (s_d1 + s_d2)) / 9,
 //     P_G = S at rest, -S/2 on axial, S/4 on diagonal directions.
-//   D3Q19: with A_a the neq sum over the two axial directions along a,
-//     D_c the neq sum over the four diagonals of the plane normal to c,
-//     X_a = A_a + D_a and Xm the mean of X:
-//     S = n_0 - 2 (A_x + A_y + A_z) + (D_x + D_y + D_z)    (isotropic mode)
+//   D3Q19: with A_a = s of the axial pair along a, D_c = sum of s over the
+//     two diagonal pairs in the plane normal to c, X_a = A_a + D_a and Xm
+//     the mean of X:
+//     S = h_0 - 2 (A_x + A_y + A_z) + (D_x + D_y + D_z)    (isotropic mode)
 //     P_G = S/6 at rest, -S/18 + (X_a - Xm)/4 on axial a,
 //           S/72 + (X_c - Xm)/8 on a diagonal in the plane normal to c.
 #pragma once
@@ -35,22 +47,54 @@
 
 namespace ptrt {
 
-template <class C>
-struct Relax {
-    C ap, am;      // 1 - 1/tau+, 1 - 1/tau-
-    C gx, gy, gz;  // body acceleration
+// Per-lattice constants of the update, computed once on the host in FP64
+// and rounded to the compute type (they are uniform across every wave, so
+// the kernels read them as scalar operands instead of recomputing them).
+template <class L, class C>
+struct Coef {
+    C ap, am, half_am;  // a+ = 1 - 1/tau+, a- = 1 - 1/tau-, a-/2
+    C cw0;              // (1 - a+) w_0
+    C cwp[2], cwm[2];   // (1 - a+) w and (1 - a-) w of axial [0] / diagonal [1] directions
+    C hgx, hgy, hgz;    // g / 2
+    C K[L::NP];         // (1 + a-) (3/2) w_i e_i.g of the first member of each pair
 };
+
+template <class L, class C>
+inline Coef<L, C> make_coef(double tau_plus, double Lambda, const double g[3])
+{
+    const double tau_minus = 0.5 + Lambda / (tau_plus - 0.5);
+    const double ap = 1.0 - 1.0 / tau_plus, am = 1.0 - 1.0 / tau_minus;
+    Coef<L, C> c{};
+    c.ap = (C)ap;
+    c.am = (C)am;
+    c.half_am = (C)(0.5 * am);
+    c.cw0 = (C)((1.0 - ap) * L::w(0));
+    for (int k = 0; k < 2; ++k) {
+        const double w = L::w(L::pair_first(k == 0 ? 0 : L::NP - 1));
+        c.cwp[k] = (C)((1.0 - ap) * w);
+        c.cwm[k] = (C)((1.0 - am) * w);
+    }
+    c.hgx = (C)(0.5 * g[0]);
+    c.hgy = (C)(0.5 * g[1]);
+    c.hgz = (C)(0.5 * g[2]);
+    for (int p = 0; p < L::NP; ++p) {
+        const int i = L::pair_first(p);
+        const double eg = L::ex(i) * g[0] + L::ey(i) * g[1] + L::ez(i) * g[2];
+        c.K[p] = (C)((1.0 + am) * 1.5 * L::w(i) * eg);
+    }
+    return c;
+}
 
 template <class L>
 struct Ghost;
 
 template <>
 struct Ghost<D2Q9> {
-    // np: neq+ per pair (axial pairs 0,1; diagonal pairs 2,3)
+    // sp: pair sums (axial pairs 0,1; diagonal pairs 2,3)
     template <class C>
-    __device__ __forceinline__ static void project(C n0, const C (&np)[4], C &pg0, C (&pg)[4])
+    __device__ __forceinline__ static void project(C h0, const C (&sp)[4], C &pg0, C (&pg)[4])
     {
-        const C S = (n0 + C(-4) * (np[0] + np[1]) + C(8) * (np[2] + np[3])) * C(1.0 / 9.0);
+        const C S = (h0 + C(-2) * (sp[0] + sp[1]) + C(4) * (sp[2] + sp[3])) * C(1.0 / 9.0);
         pg0 = S;
         pg[0] = pg[1] = C(-0.5) * S;
         pg[2] = pg[3] = C(0.25) * S;
@@ -62,13 +106,13 @@ struct Ghost<D3Q19> {
     // pairs: 0..2 axial x,y,z; 3,4 xy plane (normal z); 5,6 xz plane
     // (normal y); 7,8 yz plane (normal x)
     template <class C>
-    __device__ __forceinline__ static void project(C n0, const C (&np)[9], C &pg0, C (&pg)[9])
+    __device__ __forceinline__ static void project(C h0, const C (&sp)[9], C &pg0, C (&pg)[9])
     {
-        const C Ax = C(2) * np[0], Ay = C(2) * np[1], Az = C(2) * np[2];
-        const C Dz = C(2) * (np[3] + np[4]);
-        const C Dy = C(2) * (np[5] + np[6]);
-        const C Dx = C(2) * (np[7] + np[8]);
-        const C S = n0 - C(2) * (Ax + Ay + Az) + (Dx + Dy + Dz);
+        const C Ax = sp[0], Ay = sp[1], Az = sp[2];
+        const C Dz = sp[3] + sp[4];
+        const C Dy = sp[5] + sp[6];
+        const C Dx = sp[7] + sp[8];
+        const C S = h0 - C(2) * (Ax + Ay + Az) + (Dx + Dy + Dz);
         const C Xx = Ax + Dx, Xy = Ay + Dy, Xz = Az + Dz;
         const C Xm = (Xx + Xy + Xz) * C(1.0 / 3.0);
         const C sa = S * C(-1.0 / 18.0), sd = S * C(1.0 / 72.0);
@@ -119,46 +163,51 @@ __device__ __forceinline__ void shifted_moments(const C (&h)[L::Q], C &drho, C &
 // In-place collision of one node.  Returns rho and u through the
 // references (used by the fused diagnostics).
 template <class L, class C>
-__device__ __forceinline__ void collide(C (&h)[L::Q], const Relax<C> &r, C &rho_o, C &ux_o,
+__device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rho_o, C &ux_o,
                                         C &uy_o, C &uz_o)
 {
-    C drho, jx, jy, jz;
-    shifted_moments<L>(h, drho, jx, jy, jz);
-    const C rho = C(1) + drho;
-    const C Fx = rho * r.gx, Fy = rho * r.gy, Fz = rho * r.gz;
-    const C inv = C(1) / rho;
-    const C ux = (jx + C(0.5) * Fx) * inv;
-    const C uy = (jy + C(0.5) * Fy) * inv;
-    const C uz = (jz + C(0.5) * Fz) * inv;
-    const C uu = ux * ux + uy * uy + uz * uz;
-
-    const C w0 = C(L::w(0));
-    const C eq0 = w0 * (drho - C(1.5) * rho * uu);
-    const C n0 = h[0] - eq0;
-
-    C eqp[L::NP], eqm[L::NP], np[L::NP], nm[L::NP];
+    C sp[L::NP], dp[L::NP];
     static_for<L::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int i = L::pair_first(p), j = L::opp(i);
-        const C w = C(L::w(i));
-        const C eu = edot<L, i>(ux, uy, uz);
-        const C eu2 = eu * eu;
-        eqp[p] = w * (drho + rho * (C(4.5) * eu2 - C(1.5) * uu));
-        eqm[p] = w * rho * eu * (C(3) + C(4.5) * (eu2 - uu));
-        np[p] = C(0.5) * (h[i] + h[j]) - eqp[p];
-        nm[p] = C(0.5) * (h[i] - h[j]) - eqm[p];
+        sp[p] = h[i] + h[j];
+        dp[p] = h[i] - h[j];
     });
+    C drho = h[0], jx = C(0), jy = C(0), jz = C(0);
+    static_for<L::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = L::pair_first(p);
+        drho += sp[p];
+        if constexpr (L::ex(i) == 1) jx += dp[p];
+        if constexpr (L::ex(i) == -1) jx -= dp[p];
+        if constexpr (L::ey(i) == 1) jy += dp[p];
+        if constexpr (L::ey(i) == -1) jy -= dp[p];
+        if constexpr (L::ez(i) == 1) jz += dp[p];
+        if constexpr (L::ez(i) == -1) jz -= dp[p];
+    });
+    const C rho = C(1) + drho;
+    const C inv = C(1) / rho;
+    const C ux = jx * inv + r.hgx;
+    const C uy = jy * inv + r.hgy;
+    const C uz = jz * inv + r.hgz;
+    const C uu = ux * ux + uy * uy + uz * uz;
+    const C m15uu = C(-1.5) * uu;
 
     C pg0, pg[L::NP];
-    Ghost<L>::project(n0, np, pg0, pg);
+    Ghost<L>::project(h[0], sp, pg0, pg);
 
-    h[0] = eq0 + r.ap * (n0 - pg0);
+    h[0] = r.cw0 * (drho + rho * m15uu) + r.ap * (h[0] - pg0);
+    const C rw_m[2] = {r.cwm[0] * rho, r.cwm[1] * rho};
     static_for<L::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int i = L::pair_first(p), j = L::opp(i);
-        const C src = C(1.5 * L::w(i)) * edot<L, i>(Fx, Fy, Fz);
-        const C sym = eqp[p] + r.ap * (np[p] - pg[p]);
-        const C anti = eqm[p] + r.am * (nm[p] + src) + src;
+        constexpr int cls = L::pair_class(p);
+        const C eu = edot<L, i>(ux, uy, uz);
+        const C eu2 = eu * eu;
+        const C qp = drho + rho * (C(4.5) * eu2 + m15uu);           // heq+ / w
+        const C sym = r.cwp[cls] * qp + r.ap * (C(0.5) * sp[p] - pg[p]);
+        const C qm = eu * (C(3) + C(4.5) * (eu2 - uu));             // heq- / (w rho)
+        const C anti = rw_m[cls] * qm + (r.half_am * dp[p] + rho * r.K[p]);
         h[i] = sym + anti;
         h[j] = sym - anti;
     });

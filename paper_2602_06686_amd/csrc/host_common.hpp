@@ -79,6 +79,10 @@ inline int check_params(int lattice, int nx, int ny, int nz, double tau_plus, do
         msg = "lattice has 2^31 nodes or more";
         return PTRT_EINVAL;
     }
+    if (ny > 262140 || nz > 65535) {
+        msg = "ny must be <= 262140 and nz <= 65535 (launch grid limits)";
+        return PTRT_EINVAL;
+    }
     if (!finite(tau_plus) || !finite(Lambda) || !(tau_plus > 0.5) || !(Lambda > 0.0)) {
         msg = "need finite tau_plus > 1/2 and Lambda > 0";
         return PTRT_ETAU;
@@ -92,12 +96,23 @@ inline int check_params(int lattice, int nx, int ny, int nz, double tau_plus, do
     return PTRT_OK;
 }
 
-// tau- from Lambda = (tau+ - 1/2)(tau- - 1/2); relaxation constants 1 - 1/tau.
-inline void relaxation(double tau_plus, double Lambda, double &ap, double &am)
+// Tiled layout of a lattice (see kernels.hpp): rows per tile chosen so one
+// direction chunk of a tile is about 8 KB.  Returns the element count of a
+// population buffer and fills g.
+inline long long make_layout(int Q, int nx, int ny, int nz, size_t elem, Geom &g)
 {
-    const double tau_minus = 0.5 + Lambda / (tau_plus - 0.5);
-    ap = 1.0 - 1.0 / tau_plus;
-    am = 1.0 - 1.0 / tau_minus;
+    int lr = 0;
+    while (((long long)nx << (lr + 1)) * (long long)elem <= 8192) ++lr;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.lr = lr;
+    g.plane = (long long)nx << lr;
+    g.tile = (long long)Q * g.plane;
+    const long long rows = (long long)ny * nz;
+    const long long ntiles = (rows + (1LL << lr) - 1) >> lr;
+    return ntiles * g.tile;
 }
+
 
 } // namespace ptrt

@@ -2,12 +2,20 @@
 // state scatter used by initialisation and restore, the gather used by
 // moments / populations / diagnostics, and the FP64 reductions.
 //
-// Layout (one lattice): direction-major planes of shifted populations,
-// h[i * qs + node], node = (z * ny + y) * nx + x, x fastest.  qs >= N is the
-// plane stride.  A step pulls: population i of node x comes from node
-// x - e_i of the previous post-collision state (periodic wrap), or, when that
-// node is solid, from direction opp(i) of x itself (halfway bounce-back).
-// The stored state is therefore "post-collision at t-1, not yet streamed":
+// Layout (one lattice): rows of nx nodes (row = z * ny + y, x fastest) are
+// grouped into tiles of R = 2^lr rows; a tile stores direction 0 of its R
+// rows, then direction 1, ..., then direction Q-1, each as a contiguous
+// chunk of plane = R * nx shifted populations h_i = f_i - w_i.  Element
+// (i, row, x) sits at  (row >> lr) * Q * plane + i * plane
+// + (row & (R-1)) * nx + x.  With R large enough to hold every row this is
+// the plain direction-major (SoA) layout; with chunks of a few KB the Q
+// streams of a step stay inside one tile, which keeps the HBM pages that a
+// wave touches close together.
+//
+// A step pulls: population i of node x comes from node x - e_i of the
+// previous post-collision state (periodic wrap), or, when that node is
+// solid, from direction opp(i) of x itself (halfway bounce-back).  The
+// stored state is therefore "post-collision at t-1, not yet streamed":
 // pulling it gives the pre-collision populations at time t.
 #pragma once
 
@@ -22,20 +30,29 @@ namespace ptrt {
 
 struct Geom {
     int nx, ny, nz;
-    long long qs; // plane stride in elements
+    int lr;          // log2 of rows per tile
+    long long plane; // elements of one direction inside a tile: nx << lr
+    long long tile;  // elements of a tile: Q * plane
 };
 
-// Source node of population i pulled into (x, y, z), periodic wrap.
-template <class L, int I>
-__device__ __forceinline__ unsigned source_node(const Geom &g, int x, int y, int z, int xm,
-                                                int xp, int ym, int yp, int zm, int zp)
+// Offset of the first element of direction q of a row; element (q, row, x)
+// is at row_base(g, q, row) + x.  Kept apart from x so that, when the row is
+// uniform across a wave, the base is computed on the scalar unit and the
+// loads use a scalar base with a 32-bit per-lane offset.
+__device__ __forceinline__ long long row_base(const Geom &g, int q, unsigned row)
 {
-    const int sx = L::ex(I) == 1 ? xm : (L::ex(I) == -1 ? xp : x);
-    const int sy = L::ey(I) == 1 ? ym : (L::ey(I) == -1 ? yp : y);
-    const int sz = L::ez(I) == 1 ? zm : (L::ez(I) == -1 ? zp : z);
-    return ((unsigned)sz * (unsigned)g.ny + (unsigned)sy) * (unsigned)g.nx + (unsigned)sx;
+    return (long long)(row >> g.lr) * g.tile + (long long)q * g.plane +
+           (long long)((row & ((1u << g.lr) - 1u)) * (unsigned)g.nx);
 }
 
+template <class S>
+__device__ __forceinline__ S *at(S *base, const Geom &g, int q, unsigned row, int x)
+{
+    return (base + row_base(g, q, row)) + (unsigned)x;
+}
+
+// Source of population I pulled into (x, y, z): x coordinate and row of
+// node (x, y, z) - e_I with periodic wrap.
 struct Nbr {
     int xm, xp, ym, yp, zm, zp;
     __device__ __forceinline__ Nbr(const Geom &g, int x, int y, int z)
@@ -49,27 +66,38 @@ struct Nbr {
     }
 };
 
-// Pull the Q populations of a fluid node into registers (type T).
+template <class L, int I>
+__device__ __forceinline__ void source_of(const Geom &g, const Nbr &n, int x, int y, int z, int &sx,
+                                          unsigned &srow)
+{
+    sx = L::ex(I) == 1 ? n.xm : (L::ex(I) == -1 ? n.xp : x);
+    const int sy = L::ey(I) == 1 ? n.ym : (L::ey(I) == -1 ? n.yp : y);
+    const int sz = L::ez(I) == 1 ? n.zm : (L::ez(I) == -1 ? n.zp : z);
+    srow = (unsigned)sz * (unsigned)g.ny + (unsigned)sy;
+}
+
+// Pull the Q populations of fluid node (x, y, z) into registers (type T).
 template <class L, class S, bool MASK, class T, class LoadF>
 __device__ __forceinline__ void pull(const S *__restrict__ src, const uint8_t *__restrict__ mask,
-                                     const Geom &g, int x, int y, int z, unsigned node,
-                                     T (&h)[L::Q], LoadF load)
+                                     const Geom &g, int x, int y, int z, T (&h)[L::Q], LoadF load)
 {
     const Nbr n(g, x, y, z);
+    const unsigned row = (unsigned)z * (unsigned)g.ny + (unsigned)y;
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const S *plane = src + (long long)i * g.qs;
         if constexpr (i == 0) {
-            h[0] = load(plane + node);
+            h[0] = load(at(src, g, 0, row, x));
         } else {
-            const unsigned s = source_node<L, i>(g, x, y, z, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp);
+            int sx;
+            unsigned srow;
+            source_of<L, i>(g, n, x, y, z, sx, srow);
             if constexpr (MASK) {
-                if (mask[s])
-                    h[i] = load(src + (long long)L::opp(i) * g.qs + node);
+                if (mask[srow * (unsigned)g.nx + (unsigned)sx])
+                    h[i] = load(at(src, g, L::opp(i), row, x));
                 else
-                    h[i] = load(plane + s);
+                    h[i] = load(at(src, g, i, srow, sx));
             } else {
-                h[i] = load(plane + s);
+                h[i] = load(at(src, g, i, srow, sx));
             }
         }
     });
@@ -79,20 +107,22 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const uint8_t *_
 // the slots its next pull reads: the inverse of pull().
 template <class L, class S, bool MASK>
 __device__ __forceinline__ void scatter(S *__restrict__ dst, const uint8_t *__restrict__ mask,
-                                        const Geom &g, int x, int y, int z, unsigned node,
-                                        const double (&hv)[L::Q])
+                                        const Geom &g, int x, int y, int z, const double (&hv)[L::Q])
 {
     const Nbr n(g, x, y, z);
+    const unsigned row = (unsigned)z * (unsigned)g.ny + (unsigned)y;
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         if constexpr (i == 0) {
-            store_f64(dst + node, hv[0]);
+            store_f64(at(dst, g, 0, row, x), hv[0]);
         } else {
-            const unsigned s = source_node<L, i>(g, x, y, z, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp);
-            if (MASK && mask[s])
-                store_f64(dst + (long long)L::opp(i) * g.qs + node, hv[i]);
+            int sx;
+            unsigned srow;
+            source_of<L, i>(g, n, x, y, z, sx, srow);
+            if (MASK && mask[srow * (unsigned)g.nx + (unsigned)sx])
+                store_f64(at(dst, g, L::opp(i), row, x), hv[i]);
             else
-                store_f64(dst + (long long)i * g.qs + s, hv[i]);
+                store_f64(at(dst, g, i, srow, sx), hv[i]);
         }
     });
 }
@@ -134,30 +164,41 @@ __device__ __forceinline__ unsigned flat_block()
 // ---------------------------------------------------------------------------
 // Fused step: pull, moments, equilibrium, parity split, ghost removal,
 // two-rate relaxation, force; store to the node's own slots of dst.
-// With DIAG, also reduce mass and kinetic energy of the pulled (pre-collision)
+// ROW: 1D workgroups inside one row (grid (ceil(nx / blockDim.x), ny, nz)),
+// so y, z and every row and tile offset are uniform across the wave and
+// computed on the scalar unit; otherwise 2D workgroups over (x, y) and
+// grid.z = nz (used when ny exceeds the grid's y limit).
+// NT: non-temporal stores (the state is far larger than the caches).
+// DIAG: also reduce mass and kinetic energy of the pulled (pre-collision)
 // state into per-block FP64 partials.
-template <class L, class S, bool MASK, bool DIAG>
-__global__ void __launch_bounds__(256)
+template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG>
+__global__ void __launch_bounds__(1024)
 k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g,
-       Relax<typename Codec<S>::compute> r, double2 *__restrict__ partials)
+       Coef<L, typename Codec<S>::compute> r, double2 *__restrict__ partials)
 {
     using C = typename Codec<S>::compute;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    bool active = x < g.nx && y < g.ny;
-    const unsigned node = ((unsigned)z * (unsigned)g.ny + (unsigned)y) * (unsigned)g.nx + (unsigned)x;
-    if (MASK && active) active = mask[node] == 0;
+    int x, y, z;
+    if constexpr (ROW) {
+        x = blockIdx.x * blockDim.x + threadIdx.x;
+        y = blockIdx.y;
+        z = blockIdx.z;
+    } else {
+        x = blockIdx.x * blockDim.x + threadIdx.x;
+        y = blockIdx.y * blockDim.y + threadIdx.y;
+        z = blockIdx.z;
+    }
+    bool active = x < g.nx && (ROW || y < g.ny);
+    const unsigned row = (unsigned)z * (unsigned)g.ny + (unsigned)y;
+    if (MASK && active) active = mask[row * (unsigned)g.nx + (unsigned)x] == 0;
     double m = 0.0, k = 0.0;
     if (active) {
         C h[L::Q];
-        pull<L, S, MASK>(src, mask, g, x, y, z, node, h,
-                         [](const S *p) { return Codec<S>::load(p); });
+        pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
         C rho, ux, uy, uz;
         collide<L, C>(h, r, rho, ux, uy, uz);
         static_for<L::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            Codec<S>::store(dst + (long long)i * g.qs + node, h[i]);
+            Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);
         });
         if constexpr (DIAG) {
             m = (double)rho;
@@ -189,7 +230,7 @@ k_set_state(S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g, int z
         constexpr int i = decltype(ic)::value;
         hv[i] = f[(long long)i * fstride + in] - L::w(i);
     });
-    scatter<L, S, MASK>(dst, mask, g, x, y, z, node, hv);
+    scatter<L, S, MASK>(dst, mask, g, x, y, z, hv);
 }
 
 // Equilibrium initialisation (Eq. feq) in FP64 from rho[N] and u[3][N]
@@ -221,7 +262,7 @@ k_init_eq(S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g, int z0,
         const double poly = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu + 4.5 * eu * (eu * eu - uu);
         hv[i] = L::w(i) * ((rho - 1.0) + rho * poly);
     });
-    scatter<L, S, MASK>(dst, mask, g, x, y, z, node, hv);
+    scatter<L, S, MASK>(dst, mask, g, x, y, z, hv);
 }
 
 // ---------------------------------------------------------------------------
@@ -244,8 +285,7 @@ k_gather(const S *__restrict__ src, const uint8_t *__restrict__ mask, Geom g, in
     double m = 0.0, k = 0.0;
     if (fluid) {
         double h[L::Q];
-        pull<L, S, MASK>(src, mask, g, x, y, z, node, h,
-                         [](const S *p) { return load_f64(p); });
+        pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return load_f64(p); });
         double drho, jx, jy, jz;
         shifted_moments<L>(h, drho, jx, jy, jz);
         const double rho = 1.0 + drho;
@@ -285,7 +325,7 @@ k_gather(const S *__restrict__ src, const uint8_t *__restrict__ mask, Geom g, in
 
 // Sum nparts partials in a fixed order (deterministic) into out[0..1].
 // (A template only so that every translation unit may instantiate it.)
-template <int BLOCK = 256>
+template <int BLOCK = 1024>
 __global__ void __launch_bounds__(BLOCK)
 k_finalize(const double2 *__restrict__ partials, int nparts, double *__restrict__ out)
 {

@@ -46,6 +46,7 @@ struct D2Q9 {
         constexpr int t[4] = {1, 2, 5, 6};
         return t[p];
     }
+    __host__ __device__ static constexpr int pair_class(int p) { return p < 2 ? 0 : 1; }
     __host__ __device__ static constexpr double w(int i)
     {
         return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
@@ -76,6 +77,7 @@ struct D3Q19 {
         return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
     }
     __host__ __device__ static constexpr int pair_first(int p) { return 2 * p + 1; }
+    __host__ __device__ static constexpr int pair_class(int p) { return p < 3 ? 0 : 1; }
     __host__ __device__ static constexpr double w(int i)
     {
         return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);

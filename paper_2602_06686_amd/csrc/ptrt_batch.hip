@@ -1,8 +1,9 @@
 // Batched form of libptrt (declared in include/ptrt.h): many independent
 // D2Q9 lattices of different sizes advanced by one launch per step.
 //
-// Device layout: every instance owns Q planes of qs_k elements at element
-// offset off_k of each of the two population buffers, and nx_k * ny_k mask
+// Device layout: every instance owns a tiled population block (the layout of
+// kernels.hpp, with its own rows per tile) at element offset off_k of each
+// of the two population buffers, and nx_k * ny_k mask
 // bytes at offset moff_k of one shared mask array (zeros for instances
 // without solids).  A tile table lists (instance, x0, y0) for every
 // tile_x * tile_y tile of every instance; workgroup b handles tiles
@@ -24,9 +25,9 @@ namespace {
 
 template <class C>
 struct BInst {
-    long long off, qs, moff;
-    int nx, ny;
-    Relax<C> r;
+    long long off, moff;
+    Geom g;
+    Coef<D2Q9, C> r;
 };
 
 template <class S>
@@ -41,21 +42,19 @@ k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__re
         const BInst<C> p = inst[tl.x];
         const int x = tl.y + threadIdx.x;
         const int y = tl.z + threadIdx.y;
-        if (x < p.nx && y < p.ny) {
-            const Geom g{p.nx, p.ny, 1, p.qs};
+        if (x < p.g.nx && y < p.g.ny) {
             const uint8_t *m = mask + p.moff;
-            const unsigned node = (unsigned)y * (unsigned)p.nx + (unsigned)x;
-            if (!m[node]) {
+            if (!m[(unsigned)y * (unsigned)p.g.nx + (unsigned)x]) {
                 const S *s = src + p.off;
                 S *d = dst + p.off;
                 C h[D2Q9::Q];
-                pull<D2Q9, S, true>(s, m, g, x, y, 0, node, h,
+                pull<D2Q9, S, true>(s, m, p.g, x, y, 0, h,
                                     [](const S *q) { return Codec<S>::load(q); });
                 C rho, ux, uy, uz;
                 collide<D2Q9, C>(h, p.r, rho, ux, uy, uz);
                 static_for<D2Q9::Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    Codec<S>::store(d + (long long)i * g.qs + node, h[i]);
+                    Codec<S>::template store<true>(at(d, p.g, i, (unsigned)y, x), h[i]);
                 });
             }
         }
@@ -68,9 +67,10 @@ constexpr int BLK_X = 64, BLK_Y = 4;
 
 struct HostInst {
     int nx, ny;
-    double tau_plus, Lambda, g[3], ap, am;
+    double tau_plus, Lambda, force[3];
     bool has_mask;
-    long long off, qs, moff, N;
+    long long off, moff, N, elems;
+    Geom g;
 };
 
 } // namespace
@@ -200,7 +200,7 @@ int capture_graph(ptrt_batch *b, int parity)
     return PTRT_OK;
 }
 
-Geom inst_geom(const HostInst &h) { return Geom{h.nx, h.ny, 1, h.qs}; }
+Geom inst_geom(const HostInst &h) { return h.g; }
 
 int check_instance(ptrt_batch *b, int k)
 {
@@ -247,9 +247,8 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
         h.N = (long long)d.nx * d.ny;
         h.tau_plus = d.tau_plus;
         h.Lambda = d.Lambda;
-        for (int a = 0; a < 3; ++a) h.g[a] = d.force ? d.force[a] : 0.0;
-        h.g[2] = 0.0;
-        relaxation(d.tau_plus, d.Lambda, h.ap, h.am);
+        for (int a = 0; a < 3; ++a) h.force[a] = d.force ? d.force[a] : 0.0;
+        h.force[2] = 0.0;
         h.has_mask = false;
         mask.resize((size_t)(moff + h.N), 0);
         if (d.solid_mask)
@@ -258,12 +257,12 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
                     mask[(size_t)(moff + n)] = 1;
                     h.has_mask = true;
                 }
-        // planes padded to 256 bytes so every plane starts on a cache-line boundary
+        // every instance in the tiled layout, starting on a 256-byte boundary
+        h.elems = make_layout(9, h.nx, h.ny, 1, elem, h.g);
         const long long align = 256 / (long long)elem;
-        h.qs = ((h.N + align - 1) / align) * align;
         h.off = off;
         h.moff = moff;
-        off += 9 * h.qs;
+        off += ((h.elems + align - 1) / align) * align;
         moff += h.N;
         b->total_nodes += h.N;
     }
@@ -294,8 +293,7 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
         std::vector<BInst<C>> t(count);
         for (int k = 0; k < count; ++k) {
             const HostInst &h = b->inst[k];
-            t[k] = BInst<C>{h.off, h.qs, h.moff, h.nx, h.ny,
-                            Relax<C>{(C)h.ap, (C)h.am, (C)h.g[0], (C)h.g[1], (C)0}};
+            t[k] = BInst<C>{h.off, h.moff, h.g, make_coef<D2Q9, C>(h.tau_plus, h.Lambda, h.force)};
         }
         if (hipMalloc(&b->d_inst, sizeof(BInst<C>) * count) != hipSuccess) return PTRT_EDEVICE;
         if (hipMemcpy(b->d_inst, t.data(), sizeof(BInst<C>) * count, hipMemcpyHostToDevice) != hipSuccess)
@@ -404,8 +402,8 @@ int ptrt_batch_step_separate(ptrt_batch *b, int n)
                 using S = typename decltype(st)::type;
                 using C = typename Codec<S>::compute;
                 constexpr bool M = decltype(mk)::value;
-                const Relax<C> r{(C)h.ap, (C)h.am, (C)h.g[0], (C)h.g[1], (C)0};
-                hipLaunchKernelGGL((k_step<L, S, M, false>), grid, dim3(bx, by, 1), 0, b->stream,
+                const Coef<L, C> r = make_coef<L, C>(h.tau_plus, h.Lambda, h.force);
+                hipLaunchKernelGGL((k_step<L, S, M, false, true, false>), grid, dim3(bx, by, 1), 0, b->stream,
                                    (const S *)b->buf[b->cur] + h.off, (S *)b->buf[b->cur ^ 1] + h.off,
                                    b->d_mask + h.moff, g, r, (double2 *)nullptr);
                 return PTRT_OK;
@@ -421,15 +419,22 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
 {
     if (!b) return PTRT_EINVAL;
     static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {32, 8},
-                                    {64, 8}, {256, 1}, {128, 4}, {32, 16}};
+                                    {64, 8}, {256, 1}, {128, 4}, {32, 16}, {512, 1}};
     static const int grids[] = {0, 2048, 4096};
-    hipEvent_t e0, e1;
-    BHIPCHK(b, hipEventCreate(&e0));
-    BHIPCHK(b, hipEventCreate(&e1));
+    const size_t bytes = (size_t)b->total_elems * storage_bytes(b->storage);
+    // the trials run on a copy of the state, which is put back afterwards
+    void *saved = nullptr;
+    BHIPCHK(b, hipMalloc(&saved, bytes));
+    const int cur0 = b->cur;
+    hipError_t e = hipMemcpyAsync(saved, b->buf[cur0], bytes, hipMemcpyDeviceToDevice, b->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = 1e30f;
     int bt[4] = {b->tile_x, b->tile_y, b->blocks, b->xcd_order};
-    int rc = PTRT_OK;
-    for (const auto &sh : shapes)
+    int rc = e == hipSuccess ? PTRT_OK : bfail(b, PTRT_EDEVICE, "autotune setup failed");
+    for (const auto &sh : shapes) {
+        if (rc != PTRT_OK) break;
         for (int gsz : grids)
             for (int xo = 0; xo < 2 && rc == PTRT_OK; ++xo) {
                 rc = ptrt_batch_set_plan(b, sh[0], sh[1], gsz, xo);
@@ -452,9 +457,16 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
                     bt[3] = xo;
                 }
             }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    // 8 steps per trial keep the parity: restore the state into buffer cur0
+    b->cur = cur0;
+    e = hipMemcpyAsync(b->buf[cur0], saved, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipFree(saved);
     if (rc != PTRT_OK) return rc;
+    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("autotune restore: ") + hipGetErrorString(e));
     rc = ptrt_batch_set_plan(b, bt[0], bt[1], bt[2], bt[3]);
     if (tx_o) *tx_o = bt[0];
     if (ty_o) *ty_o = bt[1];
@@ -482,7 +494,7 @@ static int batch_download(ptrt_batch *b, int k, double *rho, double *u, double *
         constexpr bool M = decltype(mk)::value;
         hipLaunchKernelGGL((k_gather<L, S, M>), dim3((h.nx + BLK_X - 1) / BLK_X, (h.ny + BLK_Y - 1) / BLK_Y, 1),
                            dim3(BLK_X, BLK_Y, 1), 0, b->stream, (const S *)b->buf[b->cur] + h.off,
-                           b->d_mask + h.moff, g, 0, h.g[0], h.g[1], 0.0, d_rho, d_u, d_f, h.N,
+                           b->d_mask + h.moff, g, 0, h.force[0], h.force[1], 0.0, d_rho, d_u, d_f, h.N,
                            (double2 *)nullptr);
         return PTRT_OK;
     });
@@ -523,12 +535,12 @@ int ptrt_batch_diagnostics(ptrt_batch *b, double *mass, double *ke)
             using S = typename decltype(st)::type;
             constexpr bool M = decltype(mk)::value;
             hipLaunchKernelGGL((k_gather<L, S, M>), grid, dim3(BLK_X, BLK_Y, 1), 0, b->stream,
-                               (const S *)b->buf[b->cur] + h.off, b->d_mask + h.moff, g, 0, h.g[0],
-                               h.g[1], 0.0, (double *)nullptr, (double *)nullptr, (double *)nullptr,
+                               (const S *)b->buf[b->cur] + h.off, b->d_mask + h.moff, g, 0, h.force[0],
+                               h.force[1], 0.0, (double *)nullptr, (double *)nullptr, (double *)nullptr,
                                0LL, b->d_partials);
             return PTRT_OK;
         });
-        hipLaunchKernelGGL(k_finalize<256>, dim3(1), dim3(256), 0, b->stream, b->d_partials,
+        hipLaunchKernelGGL(k_finalize<1024>, dim3(1), dim3(1024), 0, b->stream, b->d_partials,
                            (int)(grid.x * grid.y), b->d_red + 2 * k);
     }
     BHIPCHK(b, hipGetLastError());

@@ -21,9 +21,9 @@ constexpr int BLK_X = 64, BLK_Y = 4; // gather / scatter workgroup shape
 struct ptrt_ctx {
     int lattice = 0, Q = 0;
     int nx = 0, ny = 0, nz = 0;
-    long long N = 0, qs = 0;
+    long long N = 0, elems = 0;
+    Geom geo{};
     double tau_plus = 0, Lambda = 0, g[3] = {0, 0, 0};
-    double ap = 0, am = 0;
     int storage = PTRT_F32;
     bool has_mask = false;
     std::vector<uint8_t> h_mask;
@@ -36,7 +36,8 @@ struct ptrt_ctx {
     hipStream_t stream = nullptr;
     bool allocated = false, initialized = false;
     long long t = 0;
-    int step_bx = 64, step_by = 4;
+    bool row_kernel = false, nt_store = false;
+    int row_bx = 256;
     std::string err = "no error";
 };
 
@@ -72,11 +73,14 @@ int ensure_allocated(ptrt_ctx *c)
 {
     if (c->allocated) return PTRT_OK;
     const size_t elem = storage_bytes(c->storage);
-    // plane stride: round up to 256 elements plus one 512-byte shift per plane
-    // so that the Q streams do not start on the same HBM channel
-    const long long pad = 512 / (long long)elem;
-    c->qs = ((c->N + 255) / 256) * 256 + pad;
-    const size_t bytes = (size_t)c->Q * (size_t)c->qs * elem;
+    c->elems = make_layout(c->Q, c->nx, c->ny, c->nz, elem, c->geo);
+    const size_t bytes = (size_t)c->elems * elem;
+    // Row workgroups covering 1 KB of each direction's row (measured best on
+    // MI355X for every storage type); non-temporal stores once the two
+    // population buffers are larger than the 256 MB last-level cache.
+    c->row_kernel = c->ny <= 65535 && c->nz <= 65535;
+    c->row_bx = std::min<int>(1024 / (int)elem, ((c->nx + 63) / 64) * 64);
+    c->nt_store = 2.0 * (double)bytes > 256.0 * 1024 * 1024;
     for (int k = 0; k < 2; ++k) {
         hipError_t e = hipMalloc(&c->buf[k], bytes);
         if (e != hipSuccess) {
@@ -97,7 +101,7 @@ int ensure_allocated(ptrt_ctx *c)
     return PTRT_OK;
 }
 
-Geom geom(const ptrt_ctx *c) { return Geom{c->nx, c->ny, c->nz, c->qs}; }
+Geom geom(const ptrt_ctx *c) { return c->geo; }
 
 // Scatter host data (equilibrium from rho/u, or populations f) into the
 // current buffer, slab by slab.
@@ -249,19 +253,11 @@ int ptrt_create(int lattice, int nx, int ny, int nz, double tau_plus, double Lam
     if (force)
         for (int a = 0; a < 3; ++a) c->g[a] = force[a];
     if (lattice == PTRT_D2Q9) c->g[2] = 0.0;
-    relaxation(tau_plus, Lambda, c->ap, c->am);
     if (solid_mask) {
         c->h_mask.assign(solid_mask, solid_mask + c->N);
         for (auto &v : c->h_mask) v = v ? 1 : 0;
         c->has_mask = std::any_of(c->h_mask.begin(), c->h_mask.end(), [](uint8_t v) { return v; });
         if (!c->has_mask) c->h_mask.clear();
-    }
-    if (nx >= 256 && nx % 256 == 0) {
-        c->step_bx = 256;
-        c->step_by = 1;
-    } else if (nx >= 128 && nx % 128 == 0) {
-        c->step_bx = 128;
-        c->step_by = 2;
     }
     *out = c;
     return PTRT_OK;
@@ -312,8 +308,9 @@ int ptrt_step(ptrt_ctx *c, int n)
     if (n < 0) return fail(c, PTRT_EINVAL, "negative step count");
     if (!c->initialized) return fail(c, PTRT_ESTATE, "ptrt_step before init");
     const Geom g = geom(c);
-    const dim3 block(c->step_bx, c->step_by, 1);
-    const dim3 grid((c->nx + c->step_bx - 1) / c->step_bx, (c->ny + c->step_by - 1) / c->step_by, c->nz);
+    const dim3 block = c->row_kernel ? dim3(c->row_bx, 1, 1) : dim3(64, 4, 1);
+    const dim3 grid = c->row_kernel ? dim3((c->nx + c->row_bx - 1) / c->row_bx, c->ny, c->nz)
+                                    : dim3((c->nx + 63) / 64, (c->ny + 3) / 4, c->nz);
     for (int k = 0; k < n; ++k) {
         const void *src = c->buf[c->cur];
         void *dst = c->buf[c->cur ^ 1];
@@ -322,9 +319,19 @@ int ptrt_step(ptrt_ctx *c, int n)
             using S = typename decltype(st)::type;
             using C = typename Codec<S>::compute;
             constexpr bool M = decltype(mk)::value;
-            const Relax<C> r{(C)c->ap, (C)c->am, (C)c->g[0], (C)c->g[1], (C)c->g[2]};
-            hipLaunchKernelGGL((k_step<L, S, M, false>), grid, block, 0, c->stream, (const S *)src,
-                               (S *)dst, c->d_mask, g, r, (double2 *)nullptr);
+            const Coef<L, C> r = make_coef<L, C>(c->tau_plus, c->Lambda, c->g);
+            auto go = [&](auto rowc, auto ntc) {
+                constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
+                hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false>), grid, block, 0, c->stream,
+                                   (const S *)src, (S *)dst, c->d_mask, g, r, (double2 *)nullptr);
+            };
+            if (c->row_kernel) {
+                if (c->nt_store) go(std::true_type{}, std::true_type{});
+                else go(std::true_type{}, std::false_type{});
+            } else {
+                if (c->nt_store) go(std::false_type{}, std::true_type{});
+                else go(std::false_type{}, std::false_type{});
+            }
             return PTRT_OK;
         });
         c->cur ^= 1;
@@ -365,7 +372,7 @@ int ptrt_diagnostics(ptrt_ctx *c, double *mass, double *ke)
                            (double *)nullptr, 0LL, c->d_partials);
         return PTRT_OK;
     });
-    hipLaunchKernelGGL(k_finalize<256>, dim3(1), dim3(256), 0, c->stream, c->d_partials, c->nparts, c->d_red);
+    hipLaunchKernelGGL(k_finalize<1024>, dim3(1), dim3(1024), 0, c->stream, c->d_partials, c->nparts, c->d_red);
     HIPCHK(c, hipGetLastError());
     double r[2];
     HIPCHK(c, hipMemcpyAsync(r, c->d_red, sizeof(r), hipMemcpyDeviceToHost, c->stream));

@@ -1,0 +1,152 @@
+"""GPU tests of the batched form: every instance evolves bit for bit like a
+single lattice with the same parameters (fused graph launch, per-lattice
+launches and any tile plan), and matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import lbm_inputs as I
+from conftest import print_case
+from oracle import analytic as A
+from oracle import ptrt as O
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2602_06686_amd.ptrt")
+
+
+def _small_specs(seed=1):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k, (nx, ny) in enumerate([(37, 23), (64, 64), (100, 41), (32, 200), (257, 9), (5, 70)]):
+        kind = k % 3
+        if kind == 0:
+            mask = I.channel_mask(nx, ny)
+            g = (float(rng.uniform(1e-6, 1e-5)), 0.0, 0.0)
+        elif kind == 1:
+            mask = I.square_obstacle_mask(nx, ny)
+            g = (float(rng.uniform(1e-6, 1e-5)), float(rng.uniform(-1e-6, 1e-6)), 0.0)
+        else:
+            mask = None
+            g = (0.0, 0.0, 0.0)
+        specs.append({"nx": nx, "ny": ny, "tau_plus": float(rng.uniform(0.55, 2.0)),
+                      "Lambda": [3 / 16, 0.25, 0.1][kind], "g": g, "mask": mask})
+    return specs
+
+
+def _init_fields(spec, seed):
+    rng = np.random.default_rng(seed)
+    rho, u = I.random_fields(rng, (1, spec["ny"], spec["nx"]), umax=0.03)
+    return rho, u[:2]
+
+
+def _single(spec, storage, rho, u, steps):
+    with P.Lattice(0, spec["nx"], spec["ny"], 1, spec["tau_plus"], spec["Lambda"],
+                   force=spec["g"], solid_mask=spec["mask"], storage=storage) as L:
+        L.init_equilibrium(rho, u)
+        L.step(steps)
+        return L.populations()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_bitwise_equals_single(storage):
+    print_case("batch bitwise vs single", storage)
+    specs = _small_specs()
+    b = P.ptrt_batch_create(specs, storage)
+    try:
+        fields = [_init_fields(s, 100 + k) for k, s in enumerate(specs)]
+        for k, (rho, u) in enumerate(fields):
+            P.ptrt_batch_init_equilibrium(b, k, rho, u)
+        P.ptrt_batch_set_plan(b, 64, 4, 0, 0)
+        P.ptrt_batch_step(b, 13)            # one graph replay of 10 steps + 3 launches
+        P.ptrt_batch_set_plan(b, 32, 8, 7, 1)
+        P.ptrt_batch_step(b, 5)              # persistent grid, XCD ordering
+        P.ptrt_batch_step_separate(b, 4)     # one launch per lattice
+        plan = P.ptrt_batch_autotune(b)      # must leave the state as it was
+        P.ptrt_batch_step(b, 2)
+        print("autotuned plan", plan)
+        for k, s in enumerate(specs):
+            ref = _single(s, storage, *fields[k], 24)
+            got = P.ptrt_batch_get_populations(b, k)
+            assert np.array_equal(got, ref), f"instance {k}"
+    finally:
+        P.ptrt_batch_destroy(b)
+
+
+def test_batch_fp64_matches_oracle():
+    print_case("batch FP64 vs oracle")
+    specs = _small_specs(seed=2)
+    b = P.ptrt_batch_create(specs, "f64")
+    try:
+        fields = [_init_fields(s, 200 + k) for k, s in enumerate(specs)]
+        for k, (rho, u) in enumerate(fields):
+            P.ptrt_batch_init_equilibrium(b, k, rho, u)
+        P.ptrt_batch_step(b, 30)
+        mg, kg = P.ptrt_batch_diagnostics(b)
+        for k, s in enumerate(specs):
+            ora = O.Lattice(O.D2Q9, s["nx"], s["ny"], 1, s["tau_plus"], s["Lambda"], g=s["g"],
+                            solid=s["mask"])
+            ora.init_equilibrium(*fields[k])
+            ora.step(30)
+            fo = ora.populations()
+            fg = P.ptrt_batch_get_populations(b, k)
+            fluid = np.ones((1, s["ny"], s["nx"]), bool) if s["mask"] is None else s["mask"] == 0
+            assert np.abs(fg[:, fluid] - fo[:, fluid]).max() < 1e-12 * np.abs(fo).max(), k
+            mo, ko = ora.diagnostics()
+            assert abs(mg[k] - mo) < 1e-12 * mo and abs(kg[k] - ko) < 1e-12 * ko
+            rho_g, u_g = P.ptrt_batch_moments(b, k)
+            rho_o, u_o = ora.moments()
+            assert np.abs(u_g - u_o).max() < 1e-13
+    finally:
+        P.ptrt_batch_destroy(b)
+
+
+def test_batch_poiseuille_instance_reaches_closed_form():
+    """A channel instance of the batch (Lambda = 3/16) converges to the exact
+    halfway-bounce-back profile, like the single lattice."""
+    print_case("batch Poiseuille instance")
+    N, nx, uc, tp = 32, 4, 0.1, 2.42
+    nu = (tp - 0.5) / 3
+    g = A.poiseuille_acceleration(N, uc, nu)
+    specs = [{"nx": nx, "ny": N + 2, "tau_plus": tp, "Lambda": 3 / 16, "g": (g, 0, 0),
+              "mask": I.channel_mask(nx, N + 2)},
+             {"nx": 48, "ny": 16, "tau_plus": 0.8, "Lambda": 0.25, "g": (0, 0, 0), "mask": None}]
+    b = P.ptrt_batch_create(specs, "f64")
+    try:
+        P.ptrt_batch_step(b, int(40 * N * N / (np.pi ** 2 * nu)) + 2000)
+        _, u = P.ptrt_batch_moments(b, 0)
+        err = A.rel_l2(u[0, 0, 1:N + 1, 0], A.poiseuille_profile(N, uc))
+        assert err < 1e-11
+    finally:
+        P.ptrt_batch_destroy(b)
+
+
+def test_full_batch_sampled_instances_vs_oracle():
+    """The benchmark batch (512 lattices, seed 260206686) with the autotuned
+    plan: 20 fused steps, then 6 sampled instances against the FP64 oracle
+    (FP32 bar 1e-5 on the populations' deviation from the weights), plus the
+    mass of every instance conserved."""
+    print_case("full 512-lattice batch, sampled")
+    specs = I.batch_specs()
+    b = P.ptrt_batch_create(specs, "f32")
+    try:
+        m0, _ = P.ptrt_batch_diagnostics(b)
+        P.ptrt_batch_autotune(b)
+        P.ptrt_batch_step(b, 20)
+        m1, _ = P.ptrt_batch_diagnostics(b)
+        assert np.abs(m1 - m0).max() < 1e-6 * m0.max()
+        w = O.lattice(O.D2Q9)[1][:, None, None, None]
+        for k in (0, 17, 255, 256, 400, 511):
+            s = specs[k]
+            ora = O.Lattice(O.D2Q9, s["nx"], s["ny"], 1, s["tau_plus"], s["Lambda"], g=s["g"],
+                            solid=s["mask"])
+            ora.init_equilibrium()
+            ora.step(20)
+            fo = ora.populations() - w
+            fg = P.ptrt_batch_get_populations(b, k) - w
+            fluid = s["mask"] == 0
+            scale = max(np.abs(fo[:, fluid]).max(), 1e-12)
+            err = np.abs(fg[:, fluid] - fo[:, fluid]).max()
+            # populations start at rest: compare to the forcing-driven deviation
+            assert err <= 1e-5 * scale + 1e-9, (k, err, scale)
+    finally:
+        P.ptrt_batch_destroy(b)
