@@ -13,8 +13,8 @@ configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64).
 algorithmic bytes per launch (2 * 19 * 4 bytes per node) over the average
 launch time, against the 8 TB/s HBM peak.  ``traffic`` is read from the
 committed rocprofv3 counter summary when it was taken on the current kernel
-sources, else null.  ``cpu_baseline`` times the FP64 C oracle on two steps of
-the same 256^3 lattice on the host cores.
+sources, else null.  ``cpu_baseline`` times the FP64 C oracle on twelve steps
+of the same 256^3 lattice on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only FORM]
                        [--no-cpu] [--copy-calibration]
@@ -154,7 +154,7 @@ def form_batch(P, torch, stream, steps, warmup):
     }
 
 
-def cpu_baseline(n=256, steps=2):
+def cpu_baseline(n=256, steps=12):
     """The FP64 C oracle, as it is, on `steps` steps of the headline lattice."""
     import lbm_inputs as I
     from oracle import ptrt as O
