@@ -7,9 +7,7 @@
 
 namespace ptrt {
 
-struct bf16_t {
-    uint16_t bits;
-};
+using bf16_t = __bf16;
 
 template <class S>
 struct Codec;
@@ -56,22 +54,14 @@ template <>
 struct Codec<bf16_t> {
     using compute = float;
     static constexpr int bytes = 2;
-    __device__ __forceinline__ static float load(const bf16_t *p)
-    {
-        return __uint_as_float(((uint32_t)p->bits) << 16);
-    }
-    __device__ __forceinline__ static uint16_t encode(float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u); // NaN stays NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (uint16_t)(u >> 16);
-    }
+    __device__ __forceinline__ static float load(const bf16_t *p) { return (float)*p; }
+    // the conversion compiles to the gfx950 float -> bf16 instruction, which
+    // rounds to nearest even and keeps NaN a NaN
     template <bool NT = false>
     __device__ __forceinline__ static void store(bf16_t *p, float v)
     {
-        const uint16_t b = encode(v);
-        if constexpr (NT) __builtin_nontemporal_store(b, &p->bits); else p->bits = b;
+        const bf16_t b = (bf16_t)v;
+        if constexpr (NT) __builtin_nontemporal_store(b, p); else *p = b;
     }
 };
 

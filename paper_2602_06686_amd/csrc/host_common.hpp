@@ -7,6 +7,7 @@
 #include <cmath>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.hpp"
 #include "ptrt.h"
@@ -94,6 +95,32 @@ inline int check_params(int lattice, int nx, int ny, int nz, double tau_plus, do
                 return PTRT_ETAU;
             }
     return PTRT_OK;
+}
+
+// Rows (row = z * ny + y) that hold a solid node or pull from one: a row is
+// marked when any row within one step in y and z (periodic) has a solid.
+inline std::vector<uint8_t> near_solid_rows(const uint8_t *mask, int nx, int ny, int nz)
+{
+    const long long rows = (long long)ny * nz;
+    std::vector<uint8_t> solid_row(rows, 0), near(rows, 0);
+    for (long long r = 0; r < rows; ++r)
+        for (int x = 0; x < nx; ++x)
+            if (mask[r * nx + x]) {
+                solid_row[r] = 1;
+                break;
+            }
+    const int dz_lo = nz > 1 ? -1 : 0, dz_hi = nz > 1 ? 1 : 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            uint8_t f = 0;
+            for (int dz = dz_lo; dz <= dz_hi && !f; ++dz)
+                for (int dy = -1; dy <= 1 && !f; ++dy) {
+                    const int zz = (z + dz + nz) % nz, yy = (y + dy + ny) % ny;
+                    f = solid_row[(long long)zz * ny + yy];
+                }
+            near[(long long)z * ny + y] = f;
+        }
+    return near;
 }
 
 // Tiled layout of a lattice (see kernels.hpp): rows per tile chosen so one

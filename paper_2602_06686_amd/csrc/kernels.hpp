@@ -162,21 +162,45 @@ __device__ __forceinline__ unsigned flat_block()
 }
 
 // ---------------------------------------------------------------------------
-// Fused step: pull, moments, equilibrium, parity split, ghost removal,
+// One node update: pull, moments, equilibrium, parity split, ghost removal,
 // two-rate relaxation, force; store to the node's own slots of dst.
+template <class L, class S, bool MASK, bool NT>
+__device__ __forceinline__ void node_update(const S *__restrict__ src, S *__restrict__ dst,
+                                            const uint8_t *__restrict__ mask, const Geom &g,
+                                            const Coef<L, typename Codec<S>::compute> &r, int x,
+                                            int y, int z, unsigned row, double &m, double &k)
+{
+    using C = typename Codec<S>::compute;
+    C h[L::Q];
+    pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
+    C rho, ux, uy, uz;
+    collide<L, C>(h, r, rho, ux, uy, uz);
+    static_for<L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);
+    });
+    m = (double)rho;
+    k = 0.5 * (double)rho * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
+}
+
+// Fused step kernel.
 // ROW: 1D workgroups inside one row (grid (ceil(nx / blockDim.x), ny, nz)),
 // so y, z and every row and tile offset are uniform across the wave and
 // computed on the scalar unit; otherwise 2D workgroups over (x, y) and
 // grid.z = nz (used when ny exceeds the grid's y limit).
+// MASK: the lattice has solid nodes.  near[row] != 0 marks rows that hold a
+// solid node or pull from one (computed on the host); only those rows read
+// the mask, every other row takes the mask-free code (a uniform branch in
+// ROW mode).
 // NT: non-temporal stores (the state is far larger than the caches).
 // DIAG: also reduce mass and kinetic energy of the pulled (pre-collision)
 // state into per-block FP64 partials.
 template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG>
 __global__ void __launch_bounds__(1024)
-k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g,
-       Coef<L, typename Codec<S>::compute> r, double2 *__restrict__ partials)
+k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+       const uint8_t *__restrict__ near, Geom g, Coef<L, typename Codec<S>::compute> r,
+       double2 *__restrict__ partials)
 {
-    using C = typename Codec<S>::compute;
     int x, y, z;
     if constexpr (ROW) {
         x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,23 +211,20 @@ k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict
         y = blockIdx.y * blockDim.y + threadIdx.y;
         z = blockIdx.z;
     }
-    bool active = x < g.nx && (ROW || y < g.ny);
+    const bool inside = x < g.nx && (ROW || y < g.ny);
     const unsigned row = (unsigned)z * (unsigned)g.ny + (unsigned)y;
-    if (MASK && active) active = mask[row * (unsigned)g.nx + (unsigned)x] == 0;
     double m = 0.0, k = 0.0;
-    if (active) {
-        C h[L::Q];
-        pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
-        C rho, ux, uy, uz;
-        collide<L, C>(h, r, rho, ux, uy, uz);
-        static_for<L::Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);
-        });
-        if constexpr (DIAG) {
-            m = (double)rho;
-            k = 0.5 * (double)rho * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
+    if constexpr (MASK) {
+        if (inside || ROW) {
+            if (near[row]) {
+                if (inside && mask[row * (unsigned)g.nx + (unsigned)x] == 0)
+                    node_update<L, S, true, NT>(src, dst, mask, g, r, x, y, z, row, m, k);
+            } else if (inside) {
+                node_update<L, S, false, NT>(src, dst, mask, g, r, x, y, z, row, m, k);
+            }
         }
+    } else if (inside) {
+        node_update<L, S, false, NT>(src, dst, mask, g, r, x, y, z, row, m, k);
     }
     if constexpr (DIAG) {
         block_sum2(m, k);

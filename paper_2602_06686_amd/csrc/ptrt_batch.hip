@@ -25,38 +25,37 @@ namespace {
 
 template <class C>
 struct BInst {
-    long long off, moff;
+    long long off, moff, noff; // populations, mask and near-solid row flags
     Geom g;
     Coef<D2Q9, C> r;
 };
 
-template <class S>
+// ONEROW: workgroups of one row segment (blockDim.y == 1), so the row is
+// uniform and the addressing runs on the scalar unit; rows not flagged as
+// near a solid take the mask-free code.
+template <class S, bool ONEROW>
 __global__ void __launch_bounds__(1024)
 k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+             const uint8_t *__restrict__ near,
              const BInst<typename Codec<S>::compute> *__restrict__ inst,
              const int4 *__restrict__ tiles, int ntiles)
 {
-    using C = typename Codec<S>::compute;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int4 tl = tiles[t];
-        const BInst<C> p = inst[tl.x];
+        const BInst<typename Codec<S>::compute> p = inst[tl.x];
         const int x = tl.y + threadIdx.x;
-        const int y = tl.z + threadIdx.y;
-        if (x < p.g.nx && y < p.g.ny) {
-            const uint8_t *m = mask + p.moff;
-            if (!m[(unsigned)y * (unsigned)p.g.nx + (unsigned)x]) {
-                const S *s = src + p.off;
-                S *d = dst + p.off;
-                C h[D2Q9::Q];
-                pull<D2Q9, S, true>(s, m, p.g, x, y, 0, h,
-                                    [](const S *q) { return Codec<S>::load(q); });
-                C rho, ux, uy, uz;
-                collide<D2Q9, C>(h, p.r, rho, ux, uy, uz);
-                static_for<D2Q9::Q>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    Codec<S>::template store<true>(at(d, p.g, i, (unsigned)y, x), h[i]);
-                });
-            }
+        const int y = ONEROW ? tl.z : tl.z + threadIdx.y;
+        if (!ONEROW && y >= p.g.ny) continue;
+        const bool inside = x < p.g.nx;
+        const uint8_t *m = mask + p.moff;
+        const S *s = src + p.off;
+        S *d = dst + p.off;
+        double dm, dk;
+        if (near[p.noff + y]) {
+            if (inside && !m[(unsigned)y * (unsigned)p.g.nx + (unsigned)x])
+                node_update<D2Q9, S, true, true>(s, d, m, p.g, p.r, x, y, 0, (unsigned)y, dm, dk);
+        } else if (inside) {
+            node_update<D2Q9, S, false, true>(s, d, m, p.g, p.r, x, y, 0, (unsigned)y, dm, dk);
         }
     }
 }
@@ -69,7 +68,7 @@ struct HostInst {
     int nx, ny;
     double tau_plus, Lambda, force[3];
     bool has_mask;
-    long long off, moff, N, elems;
+    long long off, moff, noff, N, elems;
     Geom g;
 };
 
@@ -81,7 +80,7 @@ struct ptrt_batch {
     long long total_elems = 0, total_nodes = 0, mask_bytes = 0;
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
-    uint8_t *d_mask = nullptr;
+    uint8_t *d_mask = nullptr, *d_near = nullptr;
     void *d_inst = nullptr;
     int4 *d_tiles = nullptr;
     int ntiles = 0;
@@ -166,9 +165,14 @@ void launch_fused(ptrt_batch *b, hipStream_t s)
 {
     using C = typename Codec<S>::compute;
     const int grid = b->blocks > 0 ? std::min(b->blocks, b->ntiles) : b->ntiles;
-    hipLaunchKernelGGL((k_batch_step<S>), dim3(grid), dim3(b->tile_x, b->tile_y, 1), 0, s,
-                       (const S *)b->buf[b->cur], (S *)b->buf[b->cur ^ 1], b->d_mask,
-                       (const BInst<C> *)b->d_inst, b->d_tiles, b->ntiles);
+    if (b->tile_y == 1)
+        hipLaunchKernelGGL((k_batch_step<S, true>), dim3(grid), dim3(b->tile_x, 1, 1), 0, s,
+                           (const S *)b->buf[b->cur], (S *)b->buf[b->cur ^ 1], b->d_mask, b->d_near,
+                           (const BInst<C> *)b->d_inst, b->d_tiles, b->ntiles);
+    else
+        hipLaunchKernelGGL((k_batch_step<S, false>), dim3(grid), dim3(b->tile_x, b->tile_y, 1), 0, s,
+                           (const S *)b->buf[b->cur], (S *)b->buf[b->cur ^ 1], b->d_mask, b->d_near,
+                           (const BInst<C> *)b->d_inst, b->d_tiles, b->ntiles);
     b->cur ^= 1;
 }
 
@@ -230,8 +234,8 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
     b->storage = storage;
     b->inst.resize(count);
     const size_t elem = storage_bytes(storage);
-    std::vector<uint8_t> mask;
-    long long off = 0, moff = 0;
+    std::vector<uint8_t> mask, near;
+    long long off = 0, moff = 0, noff = 0;
     for (int k = 0; k < count; ++k) {
         const ptrt_instance_desc &d = desc[k];
         std::string msg;
@@ -262,8 +266,12 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
         const long long align = 256 / (long long)elem;
         h.off = off;
         h.moff = moff;
+        h.noff = noff;
         off += ((h.elems + align - 1) / align) * align;
         moff += h.N;
+        const std::vector<uint8_t> nr = near_solid_rows(mask.data() + h.moff, h.nx, h.ny, 1);
+        near.insert(near.end(), nr.begin(), nr.end());
+        noff += h.ny;
         b->total_nodes += h.N;
     }
     b->total_elems = off;
@@ -284,7 +292,9 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
             return cleanup(PTRT_EDEVICE, "hipMemset failed");
     }
     if (hipMalloc(&b->d_mask, (size_t)moff) != hipSuccess ||
-        hipMemcpy(b->d_mask, mask.data(), (size_t)moff, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(b->d_mask, mask.data(), (size_t)moff, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc(&b->d_near, (size_t)noff) != hipSuccess ||
+        hipMemcpy(b->d_near, near.data(), (size_t)noff, hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(PTRT_EDEVICE, "mask upload failed");
     // instance table in the compute type of the storage
     int rc = dispatch(PTRT_D2Q9, storage, false, [&](auto, auto st, auto) -> int {
@@ -293,7 +303,8 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
         std::vector<BInst<C>> t(count);
         for (int k = 0; k < count; ++k) {
             const HostInst &h = b->inst[k];
-            t[k] = BInst<C>{h.off, h.moff, h.g, make_coef<D2Q9, C>(h.tau_plus, h.Lambda, h.force)};
+            t[k] = BInst<C>{h.off, h.moff, h.noff, h.g,
+                            make_coef<D2Q9, C>(h.tau_plus, h.Lambda, h.force)};
         }
         if (hipMalloc(&b->d_inst, sizeof(BInst<C>) * count) != hipSuccess) return PTRT_EDEVICE;
         if (hipMemcpy(b->d_inst, t.data(), sizeof(BInst<C>) * count, hipMemcpyHostToDevice) != hipSuccess)
@@ -405,7 +416,7 @@ int ptrt_batch_step_separate(ptrt_batch *b, int n)
                 const Coef<L, C> r = make_coef<L, C>(h.tau_plus, h.Lambda, h.force);
                 hipLaunchKernelGGL((k_step<L, S, M, false, true, false>), grid, dim3(bx, by, 1), 0, b->stream,
                                    (const S *)b->buf[b->cur] + h.off, (S *)b->buf[b->cur ^ 1] + h.off,
-                                   b->d_mask + h.moff, g, r, (double2 *)nullptr);
+                                   b->d_mask + h.moff, b->d_near + h.noff, g, r, (double2 *)nullptr);
                 return PTRT_OK;
             });
         }
@@ -418,8 +429,8 @@ int ptrt_batch_step_separate(ptrt_batch *b, int n)
 int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int *xcd_o)
 {
     if (!b) return PTRT_EINVAL;
-    static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {32, 8},
-                                    {64, 8}, {256, 1}, {128, 4}, {32, 16}, {512, 1}};
+    static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {64, 2}, {64, 4},
+                                    {128, 2}, {32, 8}, {64, 8}};
     static const int grids[] = {0, 2048, 4096};
     const size_t bytes = (size_t)b->total_elems * storage_bytes(b->storage);
     // the trials run on a copy of the state, which is put back afterwards
@@ -578,6 +589,7 @@ int ptrt_batch_destroy(ptrt_batch *b)
     for (int k = 0; k < 2; ++k)
         if (b->buf[k]) hipFree(b->buf[k]);
     if (b->d_mask) hipFree(b->d_mask);
+    if (b->d_near) hipFree(b->d_near);
     if (b->d_inst) hipFree(b->d_inst);
     if (b->d_tiles) hipFree(b->d_tiles);
     if (b->d_partials) hipFree(b->d_partials);

@@ -26,8 +26,8 @@ struct ptrt_ctx {
     double tau_plus = 0, Lambda = 0, g[3] = {0, 0, 0};
     int storage = PTRT_F32;
     bool has_mask = false;
-    std::vector<uint8_t> h_mask;
-    uint8_t *d_mask = nullptr;
+    std::vector<uint8_t> h_mask, h_near;
+    uint8_t *d_mask = nullptr, *d_near = nullptr;
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     double2 *d_partials = nullptr;
@@ -92,6 +92,9 @@ int ensure_allocated(ptrt_ctx *c)
     if (c->has_mask) {
         HIPCHK(c, hipMalloc(&c->d_mask, (size_t)c->N));
         HIPCHK(c, hipMemcpy(c->d_mask, c->h_mask.data(), (size_t)c->N, hipMemcpyHostToDevice));
+        c->h_near = near_solid_rows(c->h_mask.data(), c->nx, c->ny, c->nz);
+        HIPCHK(c, hipMalloc(&c->d_near, c->h_near.size()));
+        HIPCHK(c, hipMemcpy(c->d_near, c->h_near.data(), c->h_near.size(), hipMemcpyHostToDevice));
     }
     const dim3 gg = gather_grid(c, c->nz);
     c->nparts = gg.x * gg.y * gg.z;
@@ -323,7 +326,8 @@ int ptrt_step(ptrt_ctx *c, int n)
             auto go = [&](auto rowc, auto ntc) {
                 constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
                 hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false>), grid, block, 0, c->stream,
-                                   (const S *)src, (S *)dst, c->d_mask, g, r, (double2 *)nullptr);
+                                   (const S *)src, (S *)dst, c->d_mask, c->d_near, g, r,
+                                   (double2 *)nullptr);
             };
             if (c->row_kernel) {
                 if (c->nt_store) go(std::true_type{}, std::true_type{});
@@ -404,6 +408,7 @@ int ptrt_destroy(ptrt_ctx *c)
     for (int k = 0; k < 2; ++k)
         if (c->buf[k]) hipFree(c->buf[k]);
     if (c->d_mask) hipFree(c->d_mask);
+    if (c->d_near) hipFree(c->d_near);
     if (c->d_partials) hipFree(c->d_partials);
     if (c->d_red) hipFree(c->d_red);
     delete c;
