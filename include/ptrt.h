@@ -179,14 +179,17 @@ int ptrt_batch_set_stream(ptrt_batch *b, void *hip_stream);
 int ptrt_batch_init_equilibrium(ptrt_batch *b, int instance, const double *rho,
                                  const double *u);
 
-/* Tile plan of the fused launch: tiles of tile_x * tile_y nodes walked by a
- * grid of `blocks` workgroups (0 = one workgroup per tile; otherwise each
- * workgroup takes every blocks-th tile).  tile_x * tile_y must be 64, 128,
- * 256, 512 or 1024 with tile_x a multiple of 32.  xcd_order != 0 orders the
- * tile list so that the workgroups the hardware sends to one of the eight
- * accelerator dies (XCDs, round-robin by workgroup index) get neighbouring
- * tiles, which then share that die's L2.  Rebuilds the tile table and drops
- * any captured graph. */
+/* Tile plan of the fused launch: workgroups of tile_x * tile_y threads
+ * (64, 128, 256, 512 or 1024 threads; tile_x a multiple of 32, and of 64
+ * when tile_y == 1) walking a table of tiles; `blocks` workgroups (0 = one
+ * workgroup per tile; otherwise each workgroup takes every blocks-th tile).
+ * With tile_y == 1 a tile is a tile_x-node segment of one row, or, for rows
+ * narrower than the workgroup, as many whole rows (each rounded up to a
+ * multiple of 64 nodes) as fit; with tile_y > 1 it is a tile_x x tile_y
+ * block.  xcd_order != 0 orders the tile table so that the workgroups the
+ * hardware sends to one of the eight accelerator dies (XCDs, round-robin by
+ * workgroup index) get neighbouring tiles, which then share that die's L2.
+ * Rebuilds the tile table and drops any captured graph. */
 int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int xcd_order);
 
 /* Time the candidate plans on the device and keep the fastest; writes the

@@ -30,9 +30,15 @@ struct BInst {
     Coef<D2Q9, C> r;
 };
 
-// ONEROW: workgroups of one row segment (blockDim.y == 1), so the row is
-// uniform and the addressing runs on the scalar unit; rows not flagged as
-// near a solid take the mask-free code.
+// Tile table entries are int4 {instance, x0, y0, (nrows << 16) | wpr}.
+// ONEROW (blockDim.y == 1, blockDim.x a multiple of 64): wave w of the
+// workgroup takes row y0 + w / wpr, columns x0 + (w % wpr) * 64 + lane, for
+// w / wpr < nrows.  wpr is either the workgroup's waves (a segment of one
+// long row) or the instance's row width in waves (several whole short rows
+// per workgroup).  Every wave stays inside one row, so the row is
+// wave-uniform and the addressing runs on the scalar unit.  Otherwise
+// (2D workgroups) thread (tx, ty) takes node (x0 + tx, y0 + ty).
+// Rows not flagged as near a solid take the mask-free code.
 template <class S, bool ONEROW>
 __global__ void __launch_bounds__(1024)
 k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
@@ -43,9 +49,19 @@ k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__re
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int4 tl = tiles[t];
         const BInst<typename Codec<S>::compute> p = inst[tl.x];
-        const int x = tl.y + threadIdx.x;
-        const int y = ONEROW ? tl.z : tl.z + threadIdx.y;
-        if (!ONEROW && y >= p.g.ny) continue;
+        int x, y;
+        if constexpr (ONEROW) {
+            const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+            const int wpr = tl.w & 0xffff, nrows = tl.w >> 16;
+            const int r = w / wpr;
+            if (r >= nrows) continue;
+            y = tl.z + r;
+            x = tl.y + (w - r * wpr) * 64 + (int)(threadIdx.x & 63);
+        } else {
+            x = tl.y + threadIdx.x;
+            y = tl.z + threadIdx.y;
+            if (y >= p.g.ny) continue;
+        }
         const bool inside = x < p.g.nx;
         const uint8_t *m = mask + p.moff;
         const S *s = src + p.off;
@@ -120,7 +136,7 @@ void drop_graphs(ptrt_batch *b)
 bool valid_plan(int tx, int ty)
 {
     const int n = tx * ty;
-    return tx >= 32 && ty >= 1 && tx % 32 == 0 &&
+    return tx >= 32 && ty >= 1 && tx % 32 == 0 && (ty > 1 || tx % 64 == 0) &&
            (n == 64 || n == 128 || n == 256 || n == 512 || n == 1024);
 }
 
@@ -129,8 +145,23 @@ int build_tiles(ptrt_batch *b)
     std::vector<int4> spatial;
     for (int k = 0; k < b->count; ++k) {
         const HostInst &h = b->inst[k];
-        for (int y0 = 0; y0 < h.ny; y0 += b->tile_y)
-            for (int x0 = 0; x0 < h.nx; x0 += b->tile_x) spatial.push_back(make_int4(k, x0, y0, 0));
+        if (b->tile_y > 1) {
+            for (int y0 = 0; y0 < h.ny; y0 += b->tile_y)
+                for (int x0 = 0; x0 < h.nx; x0 += b->tile_x) spatial.push_back(make_int4(k, x0, y0, 0));
+            continue;
+        }
+        const int waves = b->tile_x / 64, row_waves = (h.nx + 63) / 64;
+        if (row_waves >= waves) {
+            // segments of tile_x nodes of one row
+            for (int y = 0; y < h.ny; ++y)
+                for (int x0 = 0; x0 < h.nx; x0 += b->tile_x)
+                    spatial.push_back(make_int4(k, x0, y, (1 << 16) | waves));
+        } else {
+            // several whole rows per workgroup
+            const int rows = waves / row_waves;
+            for (int y0 = 0; y0 < h.ny; y0 += rows)
+                spatial.push_back(make_int4(k, 0, y0, (std::min(rows, h.ny - y0) << 16) | row_waves));
+        }
     }
     const int n = (int)spatial.size();
     std::vector<int4> table(n);
@@ -138,7 +169,6 @@ int build_tiles(ptrt_batch *b)
         // table[8m + j] = spatial[j * chunk + m]: with round-robin dispatch of
         // workgroups over the 8 XCDs, die j walks the j-th contiguous chunk.
         const int chunk = (n + 7) / 8;
-        int pos = 0;
         std::vector<int4> out;
         out.reserve(n);
         for (int m = 0; m < chunk; ++m)
@@ -146,7 +176,6 @@ int build_tiles(ptrt_batch *b)
                 const long long src = (long long)j * chunk + m;
                 if (src < n) out.push_back(spatial[src]);
             }
-        (void)pos;
         table = out;
     } else {
         table = spatial;
@@ -429,8 +458,8 @@ int ptrt_batch_step_separate(ptrt_batch *b, int n)
 int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int *xcd_o)
 {
     if (!b) return PTRT_EINVAL;
-    static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {64, 2}, {64, 4},
-                                    {128, 2}, {32, 8}, {64, 8}};
+    static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {1024, 1},
+                                    {64, 2}, {64, 4}, {128, 2}, {32, 8}, {64, 8}};
     static const int grids[] = {0, 2048, 4096};
     const size_t bytes = (size_t)b->total_elems * storage_bytes(b->storage);
     // the trials run on a copy of the state, which is put back afterwards

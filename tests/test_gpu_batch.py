@@ -60,12 +60,16 @@ def test_batch_bitwise_equals_single(storage):
         P.ptrt_batch_step(b, 13)            # one graph replay of 10 steps + 3 launches
         P.ptrt_batch_set_plan(b, 32, 8, 7, 1)
         P.ptrt_batch_step(b, 5)              # persistent grid, XCD ordering
+        P.ptrt_batch_set_plan(b, 512, 1, 0, 0)
+        P.ptrt_batch_step(b, 3)              # whole short rows packed per workgroup
+        P.ptrt_batch_set_plan(b, 64, 1, 5, 1)
+        P.ptrt_batch_step(b, 3)              # one-wave row segments, persistent, XCD order
         P.ptrt_batch_step_separate(b, 4)     # one launch per lattice
         plan = P.ptrt_batch_autotune(b)      # must leave the state as it was
         P.ptrt_batch_step(b, 2)
         print("autotuned plan", plan)
         for k, s in enumerate(specs):
-            ref = _single(s, storage, *fields[k], 24)
+            ref = _single(s, storage, *fields[k], 30)
             got = P.ptrt_batch_get_populations(b, k)
             assert np.array_equal(got, ref), f"instance {k}"
     finally:
