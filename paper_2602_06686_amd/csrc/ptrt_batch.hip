@@ -481,7 +481,7 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
                 if (rc != PTRT_OK) break;
                 for (int k = 0; k < 2; ++k) launch_fused_any(b, b->stream);
                 hipEventRecord(e0, b->stream);
-                for (int k = 0; k < 6; ++k) launch_fused_any(b, b->stream);
+                for (int k = 0; k < 14; ++k) launch_fused_any(b, b->stream);
                 hipEventRecord(e1, b->stream);
                 if (hipEventSynchronize(e1) != hipSuccess) {
                     rc = bfail(b, PTRT_EDEVICE, "autotune timing failed");
@@ -500,7 +500,7 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
-    // 8 steps per trial keep the parity: restore the state into buffer cur0
+    // 16 steps per trial keep the parity: restore the state into buffer cur0
     b->cur = cur0;
     e = hipMemcpyAsync(b->buf[cur0], saved, bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

@@ -15,6 +15,7 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 constexpr int BLK_X = 64, BLK_Y = 4; // gather / scatter workgroup shape
+constexpr int GRAPH_STEPS = 20;      // even, so a replay keeps the buffer parity
 
 } // namespace
 
@@ -38,6 +39,10 @@ struct ptrt_ctx {
     long long t = 0;
     bool row_kernel = false, nt_store = false;
     int row_bx = 256;
+    // small lattices: steps replayed from captured graphs of GRAPH_STEPS launches
+    bool use_graph = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err = "no error";
 };
 
@@ -81,6 +86,8 @@ int ensure_allocated(ptrt_ctx *c)
     c->row_kernel = c->ny <= 65535 && c->nz <= 65535;
     c->row_bx = std::min<int>(1024 / (int)elem, ((c->nx + 63) / 64) * 64);
     c->nt_store = 2.0 * (double)bytes > 256.0 * 1024 * 1024;
+    // below ~32 MB per step a launch costs about as much as its work
+    c->use_graph = 2.0 * (double)bytes < 32.0 * 1024 * 1024;
     for (int k = 0; k < 2; ++k) {
         hipError_t e = hipMalloc(&c->buf[k], bytes);
         if (e != hipSuccess) {
@@ -222,6 +229,60 @@ int download_state(ptrt_ctx *c, double *rho, double *u, double *f)
     return rc;
 }
 
+// Enqueue one fused step on stream s (buffer cur -> cur ^ 1).
+void launch_step(ptrt_ctx *c, hipStream_t s)
+{
+    const Geom g = geom(c);
+    const dim3 block = c->row_kernel ? dim3(c->row_bx, 1, 1) : dim3(64, 4, 1);
+    const dim3 grid = c->row_kernel ? dim3((c->nx + c->row_bx - 1) / c->row_bx, c->ny, c->nz)
+                                    : dim3((c->nx + 63) / 64, (c->ny + 3) / 4, c->nz);
+    const void *src = c->buf[c->cur];
+    void *dst = c->buf[c->cur ^ 1];
+    dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
+        using L = typename decltype(lt)::type;
+        using S = typename decltype(st)::type;
+        using C = typename Codec<S>::compute;
+        constexpr bool M = decltype(mk)::value;
+        const Coef<L, C> r = make_coef<L, C>(c->tau_plus, c->Lambda, c->g);
+        auto go = [&](auto rowc, auto ntc) {
+            constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
+            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false>), grid, block, 0, s, (const S *)src,
+                               (S *)dst, c->d_mask, c->d_near, g, r, (double2 *)nullptr);
+        };
+        if (c->row_kernel) {
+            if (c->nt_store) go(std::true_type{}, std::true_type{});
+            else go(std::true_type{}, std::false_type{});
+        } else {
+            if (c->nt_store) go(std::false_type{}, std::true_type{});
+            else go(std::false_type{}, std::false_type{});
+        }
+        return PTRT_OK;
+    });
+    c->cur ^= 1;
+}
+
+// Capture GRAPH_STEPS steps starting from buffer `parity` into graph[parity].
+int capture_graph(ptrt_ctx *c, int parity)
+{
+    if (!c->capture_stream)
+        HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    const int saved = c->cur;
+    c->cur = parity;
+    hipGraph_t gr = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_STEPS; ++k) launch_step(c, c->capture_stream);
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &gr);
+    c->cur = saved;
+    if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph[parity], gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+        c->graph[parity] = nullptr;
+        return fail(c, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return PTRT_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -310,37 +371,17 @@ int ptrt_step(ptrt_ctx *c, int n)
     if (!c) return PTRT_EINVAL;
     if (n < 0) return fail(c, PTRT_EINVAL, "negative step count");
     if (!c->initialized) return fail(c, PTRT_ESTATE, "ptrt_step before init");
-    const Geom g = geom(c);
-    const dim3 block = c->row_kernel ? dim3(c->row_bx, 1, 1) : dim3(64, 4, 1);
-    const dim3 grid = c->row_kernel ? dim3((c->nx + c->row_bx - 1) / c->row_bx, c->ny, c->nz)
-                                    : dim3((c->nx + 63) / 64, (c->ny + 3) / 4, c->nz);
-    for (int k = 0; k < n; ++k) {
-        const void *src = c->buf[c->cur];
-        void *dst = c->buf[c->cur ^ 1];
-        dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
-            using L = typename decltype(lt)::type;
-            using S = typename decltype(st)::type;
-            using C = typename Codec<S>::compute;
-            constexpr bool M = decltype(mk)::value;
-            const Coef<L, C> r = make_coef<L, C>(c->tau_plus, c->Lambda, c->g);
-            auto go = [&](auto rowc, auto ntc) {
-                constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
-                hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false>), grid, block, 0, c->stream,
-                                   (const S *)src, (S *)dst, c->d_mask, c->d_near, g, r,
-                                   (double2 *)nullptr);
-            };
-            if (c->row_kernel) {
-                if (c->nt_store) go(std::true_type{}, std::true_type{});
-                else go(std::true_type{}, std::false_type{});
-            } else {
-                if (c->nt_store) go(std::false_type{}, std::true_type{});
-                else go(std::false_type{}, std::false_type{});
-            }
-            return PTRT_OK;
-        });
-        c->cur ^= 1;
-    }
     c->t += n;
+    if (c->use_graph)
+        while (n >= GRAPH_STEPS) {
+            if (!c->graph[c->cur]) {
+                int rc = capture_graph(c, c->cur);
+                if (rc != PTRT_OK) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+            n -= GRAPH_STEPS;
+        }
+    for (; n > 0; --n) launch_step(c, c->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return PTRT_OK;
@@ -409,6 +450,9 @@ int ptrt_destroy(ptrt_ctx *c)
         if (c->buf[k]) hipFree(c->buf[k]);
     if (c->d_mask) hipFree(c->d_mask);
     if (c->d_near) hipFree(c->d_near);
+    for (auto &gx : c->graph)
+        if (gx) hipGraphExecDestroy(gx);
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
     if (c->d_partials) hipFree(c->d_partials);
     if (c->d_red) hipFree(c->d_red);
     delete c;
