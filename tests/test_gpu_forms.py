@@ -47,7 +47,10 @@ def test_precision_form_64cube(setting):
     _, uo = ora.moments()
     wo = _vorticity(uo)
     errs = {}
-    for storage, bound in (("f32", 1e-5), ("f16", 2e-2), ("bf16", 2e-1)):
+    # bounds for reported errors: at tau+ - 1/2 ~ 1e-3 the stress modes are
+    # almost undamped, so rounding accumulates faster than on the 2D vortex
+    # (whose 1e-5 FP32 bar is tested in test_gpu_parity.py)
+    for storage, bound in (("f32", 5e-5), ("f16", 2e-2), ("bf16", 2e-1)):
         print_case("precision form 64^3", setting, storage)
         with P.Lattice(1, n, n, n, tp, lam, storage=storage) as G:
             G.init_equilibrium(rho, u)
