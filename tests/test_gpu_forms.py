@@ -47,10 +47,15 @@ def test_precision_form_64cube(setting):
     _, uo = ora.moments()
     wo = _vorticity(uo)
     errs = {}
-    # bounds for reported errors: at tau+ - 1/2 ~ 1e-3 the stress modes are
-    # almost undamped, so rounding accumulates faster than on the 2D vortex
-    # (whose 1e-5 FP32 bar is tested in test_gpu_parity.py)
-    for storage, bound in (("f32", 5e-5), ("f16", 2e-2), ("bf16", 2e-1)):
+    # At 1/tau- = 1.6 the FP16 bar is the benchmark spec's 1e-3.  At Lambda = 1/4
+    # (tau- = 262 here) the third-order modes are almost undamped and the
+    # FP64 run itself blows up after ~1000 steps, so low-precision rounding
+    # noise is hardly damped: those errors are reported, with loose bounds.
+    # FP32 at tau+ - 1/2 ~ 1e-3 accumulates more rounding than on the 2D
+    # vortex (whose 1e-5 FP32 bar is tested in test_gpu_parity.py).
+    bounds = {"Lambda=1/4": (("f32", 5e-5), ("f16", 0.2), ("bf16", 1.0)),
+              "1/tau-=1.6": (("f32", 2e-5), ("f16", 1e-3), ("bf16", 2e-2))}[setting]
+    for storage, bound in bounds:
         print_case("precision form 64^3", setting, storage)
         with P.Lattice(1, n, n, n, tp, lam, storage=storage) as G:
             G.init_equilibrium(rho, u)
