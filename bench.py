@@ -94,12 +94,19 @@ def bench_single(P, torch, stream, lattice, shape, storage, init, tau_plus, Lamb
     return res
 
 
-def form_d3q19(P, torch, stream, n, storage, steps, warmup, diag=False):
+def form_d3q19(P, torch, stream, n, storage, steps, warmup, diag=False, inv_tau_minus=None):
+    """D3Q19 3D Taylor-Green vortex; Lambda = 1/4, or the Lambda giving a
+    fixed 1/tau- (the paper's stability optimum 1.6, used for the precision
+    form, where Lambda = 1/4 makes the flow itself unstable)."""
     import lbm_inputs as I
     prm = I.tgv3d_params(n)
+    tp = prm["tau_plus"]
+    lam = 0.25 if inv_tau_minus is None else I.tau_minus_from_inverse(inv_tau_minus, tp)
     r = bench_single(P, torch, stream, P.PTRT_D3Q19, (n, n, n), storage,
-                     lambda: I.tgv3d(n, 0.05), prm["tau_plus"], 0.25, steps, warmup, diag=diag)
-    r["workload"] = f"D3Q19 P-TRT {storage.upper()} {n}^3 periodic 3D Taylor-Green vortex (U0=0.05, Re=1600, Lambda=1/4)"
+                     lambda: I.tgv3d(n, 0.05), tp, lam, steps, warmup, diag=diag)
+    setting = "Lambda=1/4" if inv_tau_minus is None else f"1/tau-={inv_tau_minus}"
+    r["workload"] = (f"D3Q19 P-TRT {storage.upper()} {n}^3 periodic 3D Taylor-Green vortex "
+                     f"(U0=0.05, Re=1600, {setting})")
     return r
 
 
@@ -154,6 +161,33 @@ def form_batch(P, torch, stream, steps, warmup):
     }
 
 
+def form_models(P, torch, stream, steps, warmup):
+    """P-TRT against TRT-RLB (Hermite projection) and standard TRT kernels in
+    the same harness: the paper's efficiency comparison (Table efficiency)
+    on this GPU, for the D2Q9 shear layer and the D3Q19 vortex (FP32)."""
+    import lbm_inputs as I
+    out = {}
+    n2, U0 = 2048, 0.05
+    tp2 = I.tau_plus_from_nu(U0 * n2 / 1e4)
+    n3 = 256
+    tp3 = I.tgv3d_params(n3)["tau_plus"]
+    for lat, shape, tp, init, key in (
+            (P.PTRT_D2Q9, (1, n2, n2), tp2, lambda: I.double_shear_layer(n2, U0), "d2q9_2048_dsl"),
+            (P.PTRT_D3Q19, (n3, n3, n3), tp3, lambda: I.tgv3d(n3, U0), "d3q19_256_tgv")):
+        nz, ny, nx = shape
+        rho, u = init()
+        res = {}
+        for model in ("ptrt", "trt-rlb", "trt"):
+            with P.Lattice(lat, nx, ny, nz, tp, 0.25, storage="f32", stream=stream, model=model) as L:
+                L.init_equilibrium(rho, u)
+                ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+                res[model] = {"ms_per_step": ms / steps, "mlups": nx * ny * nz * steps / (ms * 1e-3) / 1e6}
+        res["trt_rlb_time_over_ptrt"] = res["trt-rlb"]["ms_per_step"] / res["ptrt"]["ms_per_step"]
+        res["trt_time_over_ptrt"] = res["trt"]["ms_per_step"] / res["ptrt"]["ms_per_step"]
+        out[key] = res
+    return out
+
+
 def cpu_baseline(n=256, steps=12):
     """The FP64 C oracle, as it is, on `steps` steps of the headline lattice."""
     import lbm_inputs as I
@@ -200,7 +234,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default=None,
-                    help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, tgv64")
+                    help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, models, tgv64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -229,7 +263,8 @@ def main():
     if only in (None, "d3q19_512"):
         for st in ("f32", "f16", "bf16"):
             log(f"D3Q19 {st} 512^3")
-            forms[f"d3q19_512_{st}"] = form_d3q19(P, torch, stream, 512, st, max(20, K // 2), max(2, W // 2))
+            forms[f"d3q19_512_{st}"] = form_d3q19(P, torch, stream, 512, st, max(20, K // 2),
+                                                  max(2, W // 2), inv_tau_minus=1.6)
             log(json.dumps(forms[f"d3q19_512_{st}"]))
         f32 = forms["d3q19_512_f32"]["mlups"]
         forms["fp16_over_fp32_512"] = forms["d3q19_512_f16"]["mlups"] / f32
@@ -241,6 +276,10 @@ def main():
     if only in (None, "dsl2048"):
         log("D2Q9 FP32 2048^2")
         forms["d2q9_2048_f32"] = form_dsl(P, torch, stream, K, W)
+    if only in (None, "models"):
+        log("collision models")
+        forms["models_fp32"] = form_models(P, torch, stream, max(20, K // 2), max(2, W // 2))
+        log(json.dumps(forms["models_fp32"]))
     if only in (None, "tgv64"):
         log("D2Q9 FP64 64^2")
         forms["d2q9_64_f64"] = form_tgv64(P, torch, stream, 1000, 50)

@@ -74,6 +74,16 @@ enum ptrt_lattice { PTRT_D2Q9 = 0, PTRT_D3Q19 = 1 };
 
 enum ptrt_storage { PTRT_F64 = 0, PTRT_F32 = 1, PTRT_F16 = 2, PTRT_BF16 = 3 };
 
+/* Collision model of ptrt_step: P-TRT (the method, Eq. PTRT) or, for
+ * comparison, TRT-RLB (Eq. TRT-RLB: Hermite projection of the
+ * non-equilibrium part, Eq. R2R3_hermite, with tau+ also on the first-order
+ * moment and the Scheme II source without G_i; on D3Q19 the third-order
+ * reconstruction is the orthogonal projection onto the third-order modes)
+ * or standard TRT (P-TRT without the ghost subtraction: the ghost modes
+ * relax with tau+, Eq. collision_TRT).  All three share the state layout,
+ * the streaming and the force convention. */
+enum ptrt_model { PTRT_MODEL_PTRT = 0, PTRT_MODEL_TRT_RLB = 1, PTRT_MODEL_TRT = 2 };
+
 enum ptrt_status {
     PTRT_OK = 0,
     PTRT_EINVAL = -1,    /* bad lattice id, size, pointer or argument */
@@ -101,6 +111,11 @@ int ptrt_create(int lattice, int nx, int ny, int nz, double tau_plus, double Lam
 /* Choose the storage type (enum ptrt_storage).  Only before the first init
  * or set_populations; PTRT_ESTATE afterwards. */
 int ptrt_set_storage(ptrt_ctx *ctx, int storage);
+
+/* Select the collision model (enum ptrt_model) for later steps; allowed at
+ * any time (waits for the handle's stream).  The comparison models need
+ * ny <= 65535 and nz <= 65535.  Default PTRT_MODEL_PTRT. */
+int ptrt_set_model(ptrt_ctx *ctx, int model);
 
 /* Stream for all later work of this handle; a hipStream_t passed as void*
  * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */

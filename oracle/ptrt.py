@@ -42,6 +42,12 @@ def _load():
         lib.ptrt_oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         _dp, _u8p, _dp, ctypes.c_int, ctypes.c_int]
+        lib.ptrt_oracle_run_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, _dp, _u8p, _dp, ctypes.c_int,
+                                              ctypes.c_int]
+        lib.ptrt_oracle_collide_trt.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                                ctypes.c_double, ctypes.c_double, _dp]
         lib.ptrt_oracle_step_sampled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                                  _dp, _u8p, _dp, ctypes.c_int, _llp, _dp]
@@ -111,6 +117,15 @@ def collide(lat, f, g, tau_plus, Lambda=None, tau_minus=None):
     return out
 
 
+def collide_trt(lat, f, g, tau_plus, tau_minus):
+    """Standard TRT (no ghost subtraction) of independent nodes, [n,Q] -> [n,Q]."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
+    out = np.zeros_like(f)
+    _load().ptrt_oracle_collide_trt(lat, f.shape[0], _p(f), _p(_g3(g)), tau_plus, tau_minus,
+                                    _p(out))
+    return out
+
+
 def node_moments(lat, f, g=None):
     """rho [n], u [n,3] of independent nodes f [n,Q] (Eq. macro)."""
     f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
@@ -129,8 +144,9 @@ class Lattice:
     """
 
     def __init__(self, lat, nx, ny, nz, tau_plus, Lambda, g=None, solid=None,
-                 tau_minus=None, nthreads=0):
+                 tau_minus=None, nthreads=0, model=0):
         self.lat = lat
+        self.model = int(model)  # 0: P-TRT, 2: standard TRT
         self.Q = _Q[lat]
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
@@ -167,9 +183,9 @@ class Lattice:
     def step(self, n=1):
         nz, ny, nx = self.shape
         solid = _p(self.solid, _u8p) if self.solid is not None else None
-        rc = _load().ptrt_oracle_run(self.lat, nx, ny, nz, self.tau_plus, self.Lambda,
-                                     self.tau_minus, _p(self.g), solid, _p(self.f),
-                                     int(n), self.nthreads)
+        rc = _load().ptrt_oracle_run_model(self.lat, self.model, nx, ny, nz, self.tau_plus,
+                                           self.Lambda, self.tau_minus, _p(self.g), solid,
+                                           _p(self.f), int(n), self.nthreads)
         if rc != 0:
             raise RuntimeError(f"oracle run failed ({rc})")
         self.t += n

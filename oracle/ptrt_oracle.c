@@ -31,6 +31,8 @@
  *     (weighted inner product sum_i w_i a_i b_i).  On D2Q9 the single
  *     product is already orthogonal and is left unchanged.
  *  R4 (force) F = rho g with g a constant acceleration (Sec. 3.3).
+ *  Standard TRT (Eq. collision_TRT), used only as a comparison model, is
+ *     the same update without the ghost subtraction.
  *  R5 (time step) collide, then stream (left side of Eq. PTRT); halfway
  *     bounce-back sends a population whose target node is solid back into
  *     the opposite direction of its source node (Sec. 3.3).
@@ -250,16 +252,21 @@ static void ghost_projection(const Lattice *L, const double *fneq, double *pg)
     }
 }
 
-/* One P-TRT collision, Eq. PTRT with R1: f -> f*. */
-static void collide(const Lattice *L, const double *f, const double g[3],
-                    double tau_p, double tau_m, double *fstar)
+/* One P-TRT collision, Eq. PTRT with R1: f -> f*.  With ghost == 0 the
+ * ghost subtraction is skipped, which is standard TRT (Eq. collision_TRT:
+ * the ghost modes relax with tau+ like the stress modes). */
+static void collide_model(const Lattice *L, const double *f, const double g[3],
+                          double tau_p, double tau_m, int ghost, double *fstar)
 {
     double rho, u[3], feq[QMAX], fneq[QMAX], plus[QMAX], minus[QMAX], pg[QMAX];
     moments(L, f, g, &rho, u);
     equilibrium(L, rho, u, feq);
     for (int i = 0; i < L->Q; ++i) fneq[i] = f[i] - feq[i];
     parity_split(L, fneq, plus, minus);
-    ghost_projection(L, fneq, pg);
+    if (ghost)
+        ghost_projection(L, fneq, pg);
+    else
+        for (int i = 0; i < L->Q; ++i) pg[i] = 0.0;
     double F[3] = {rho * g[0], rho * g[1], rho * g[2]};
     for (int i = 0; i < L->Q; ++i) {
         double eF = L->e[i][0] * F[0] + L->e[i][1] * F[1] + L->e[i][2] * F[2];
@@ -268,6 +275,12 @@ static void collide(const Lattice *L, const double *f, const double g[3],
         double R3 = minus[i] + half_force;     /* Eq. R3_force */
         fstar[i] = feq[i] + (1.0 - 1.0 / tau_p) * R2 + (1.0 - 1.0 / tau_m) * R3 + half_force;
     }
+}
+
+static void collide(const Lattice *L, const double *f, const double g[3], double tau_p,
+                    double tau_m, double *fstar)
+{
+    collide_model(L, f, g, tau_p, tau_m, 1, fstar);
 }
 
 /* tau_{s,2} from the magic parameter Lambda = (tau+ - 1/2)(tau- - 1/2). */
@@ -359,9 +372,9 @@ static int wrap(int v, int n) { return ((v % n) + n) % n; }
  * and halfway bounce-back at solid neighbours (R5).  Populations stored at
  * solid nodes are not touched.  tau_minus <= 0 means "derive from Lambda".
  */
-int ptrt_oracle_run(int id, int nx, int ny, int nz, double tau_plus, double Lambda,
-                    double tau_minus, const double g[3], const uint8_t *solid,
-                    double *f, int nsteps, int nthreads)
+int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_plus,
+                          double Lambda, double tau_minus, const double g[3],
+                          const uint8_t *solid, double *f, int nsteps, int nthreads)
 {
     Lattice L;
     if (make_lattice(id, &L)) return -1;
@@ -381,7 +394,7 @@ int ptrt_oracle_run(int id, int nx, int ny, int nz, double tau_plus, double Lamb
 #pragma omp parallel for schedule(static)
         for (long long m = 0; m < (long long)N; ++m) {
             if (solid && solid[m]) continue;
-            collide(&L, f + m * Q, g, tau_plus, tau_m, fstar + m * Q);
+            collide_model(&L, f + m * Q, g, tau_plus, tau_m, model == 0, fstar + m * Q);
         }
         /* streaming, left side of Eq. PTRT, with halfway bounce-back */
 #pragma omp parallel for schedule(static)
@@ -400,6 +413,26 @@ int ptrt_oracle_run(int id, int nx, int ny, int nz, double tau_plus, double Lamb
         }
     }
     free(fstar);
+    return 0;
+}
+
+/* model 0: P-TRT, model 2: standard TRT (no ghost subtraction). */
+int ptrt_oracle_run(int id, int nx, int ny, int nz, double tau_plus, double Lambda,
+                    double tau_minus, const double g[3], const uint8_t *solid,
+                    double *f, int nsteps, int nthreads)
+{
+    return ptrt_oracle_run_model(id, 0, nx, ny, nz, tau_plus, Lambda, tau_minus, g, solid, f,
+                                 nsteps, nthreads);
+}
+
+/* Standard TRT collision of n independent nodes (no ghost subtraction). */
+int ptrt_oracle_collide_trt(int id, int n, const double *f_in, const double g[3],
+                            double tau_plus, double tau_minus, double *f_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    for (int m = 0; m < n; ++m)
+        collide_model(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_minus, 0, f_out + (size_t)m * L.Q);
     return 0;
 }
 

@@ -59,6 +59,7 @@ struct Coef {
     C ap, am;           // a+ = 1 - 1/tau+, a- = 1 - 1/tau-
     C hgx, hgy, hgz;    // g / 2
     C K[L::NP];         // (1 + a-) (3/2) w_i e_i.g of the first member of each pair
+    C K2[L::NP];        // 3 (1 - 1/(2 tau+)) w_i e_i.g (Scheme II source, TRT-RLB form)
 };
 
 template <class L, class C>
@@ -76,6 +77,7 @@ inline Coef<L, C> make_coef(double tau_plus, double Lambda, const double g[3])
         const int i = L::pair_first(p);
         const double eg = L::ex(i) * g[0] + L::ey(i) * g[1] + L::ez(i) * g[2];
         c.K[p] = (C)((1.0 + am) * 1.5 * L::w(i) * eg);
+        c.K2[p] = (C)(3.0 * (1.0 - 0.5 / tau_plus) * L::w(i) * eg);
     }
     return c;
 }
@@ -157,7 +159,9 @@ __device__ __forceinline__ void shifted_moments(const C (&h)[L::Q], C &drho, C &
 
 // In-place collision of one node.  Returns rho and u through the
 // references (used by the fused diagnostics).
-template <class L, class C>
+// GHOST = false gives standard TRT (Eq. collision_TRT: the ghost modes
+// relax with tau+ like the stress modes); same force treatment.
+template <class L, class C, bool GHOST = true>
 __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rho_o, C &ux_o,
                                         C &uy_o, C &uz_o)
 {
@@ -188,8 +192,12 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
     const C uu = ux * ux + uy * uy + uz * uz;
     const C m15uu = C(-1.5) * uu;
 
-    C pg0, pg[L::NP];
-    Ghost<L>::project(h[0], sp, pg0, pg);
+    C pg0 = C(0), pg[L::NP];
+    if constexpr (GHOST) {
+        Ghost<L>::project(h[0], sp, pg0, pg);
+    } else {
+        for (int p = 0; p < L::NP; ++p) pg[p] = C(0);
+    }
 
     const C eq0 = C(L::w(0)) * (drho + rho * m15uu);
     h[0] = eq0 + r.ap * ((h[0] - eq0) - pg0);

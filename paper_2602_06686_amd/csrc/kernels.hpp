@@ -25,6 +25,7 @@
 #include "codec.hpp"
 #include "collide.hpp"
 #include "lattice.hpp"
+#include "trt_rlb.hpp"
 
 namespace ptrt {
 
@@ -161,10 +162,14 @@ __device__ __forceinline__ unsigned flat_block()
     return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
+// Collision models: P-TRT (the method), and for comparison TRT-RLB (Hermite
+// projection, Eq. TRT-RLB) and standard TRT (ghost modes kept).
+enum { MODEL_PTRT = 0, MODEL_TRT_RLB = 1, MODEL_TRT = 2 };
+
 // ---------------------------------------------------------------------------
 // One node update: pull, moments, equilibrium, parity split, ghost removal,
 // two-rate relaxation, force; store to the node's own slots of dst.
-template <class L, class S, bool MASK, bool NT>
+template <class L, class S, bool MASK, bool NT, int MODEL = MODEL_PTRT>
 __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__restrict__ dst,
                                             const uint8_t *__restrict__ mask, const Geom &g,
                                             const Coef<L, typename Codec<S>::compute> &r, int x,
@@ -174,7 +179,10 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
     C h[L::Q];
     pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
     C rho, ux, uy, uz;
-    collide<L, C>(h, r, rho, ux, uy, uz);
+    if constexpr (MODEL == MODEL_TRT_RLB)
+        collide_trt_rlb<L, C>(h, r, rho, ux, uy, uz);
+    else
+        collide<L, C, MODEL == MODEL_PTRT>(h, r, rho, ux, uy, uz);
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);
@@ -195,7 +203,7 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
 // NT: non-temporal stores (the state is far larger than the caches).
 // DIAG: also reduce mass and kinetic energy of the pulled (pre-collision)
 // state into per-block FP64 partials.
-template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG>
+template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG, int MODEL = MODEL_PTRT>
 __global__ void __launch_bounds__(1024)
 k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
        const uint8_t *__restrict__ near, Geom g, Coef<L, typename Codec<S>::compute> r,
@@ -218,13 +226,13 @@ k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict
         if (inside || ROW) {
             if (near[row]) {
                 if (inside && mask[row * (unsigned)g.nx + (unsigned)x] == 0)
-                    node_update<L, S, true, NT>(src, dst, mask, g, r, x, y, z, row, m, k);
+                    node_update<L, S, true, NT, MODEL>(src, dst, mask, g, r, x, y, z, row, m, k);
             } else if (inside) {
-                node_update<L, S, false, NT>(src, dst, mask, g, r, x, y, z, row, m, k);
+                node_update<L, S, false, NT, MODEL>(src, dst, mask, g, r, x, y, z, row, m, k);
             }
         }
     } else if (inside) {
-        node_update<L, S, false, NT>(src, dst, mask, g, r, x, y, z, row, m, k);
+        node_update<L, S, false, NT, MODEL>(src, dst, mask, g, r, x, y, z, row, m, k);
     }
     if constexpr (DIAG) {
         block_sum2(m, k);

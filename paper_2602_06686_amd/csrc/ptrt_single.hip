@@ -39,6 +39,7 @@ struct ptrt_ctx {
     long long t = 0;
     bool row_kernel = false, nt_store = false;
     int row_bx = 256;
+    int model = MODEL_PTRT;
     // small lattices: steps replayed from captured graphs of GRAPH_STEPS launches
     bool use_graph = false;
     hipStream_t capture_stream = nullptr;
@@ -83,7 +84,6 @@ int ensure_allocated(ptrt_ctx *c)
     // Row workgroups covering 1 KB of each direction's row (measured best on
     // MI355X for every storage type); non-temporal stores once the two
     // population buffers are larger than the 256 MB last-level cache.
-    c->row_kernel = c->ny <= 65535 && c->nz <= 65535;
     c->row_bx = std::min<int>(1024 / (int)elem, ((c->nx + 63) / 64) * 64);
     c->nt_store = 2.0 * (double)bytes > 256.0 * 1024 * 1024;
     // below ~32 MB per step a launch costs about as much as its work
@@ -244,17 +244,28 @@ void launch_step(ptrt_ctx *c, hipStream_t s)
         using C = typename Codec<S>::compute;
         constexpr bool M = decltype(mk)::value;
         const Coef<L, C> r = make_coef<L, C>(c->tau_plus, c->Lambda, c->g);
-        auto go = [&](auto rowc, auto ntc) {
+        auto go = [&](auto rowc, auto ntc, auto mc) {
             constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
-            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false>), grid, block, 0, s, (const S *)src,
-                               (S *)dst, c->d_mask, c->d_near, g, r, (double2 *)nullptr);
+            constexpr int MD = decltype(mc)::value;
+            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false, MD>), grid, block, 0, s,
+                               (const S *)src, (S *)dst, c->d_mask, c->d_near, g, r,
+                               (double2 *)nullptr);
         };
-        if (c->row_kernel) {
-            if (c->nt_store) go(std::true_type{}, std::true_type{});
-            else go(std::true_type{}, std::false_type{});
+        using P0 = std::integral_constant<int, MODEL_PTRT>;
+        using P1 = std::integral_constant<int, MODEL_TRT_RLB>;
+        using P2 = std::integral_constant<int, MODEL_TRT>;
+        auto with_nt = [&](auto rowc, auto mc) {
+            if (c->nt_store) go(rowc, std::true_type{}, mc);
+            else go(rowc, std::false_type{}, mc);
+        };
+        if (!c->row_kernel) {
+            with_nt(std::false_type{}, P0{}); // comparison models need row workgroups
+        } else if (c->model == MODEL_TRT_RLB) {
+            with_nt(std::true_type{}, P1{});
+        } else if (c->model == MODEL_TRT) {
+            with_nt(std::true_type{}, P2{});
         } else {
-            if (c->nt_store) go(std::false_type{}, std::true_type{});
-            else go(std::false_type{}, std::false_type{});
+            with_nt(std::true_type{}, P0{});
         }
         return PTRT_OK;
     });
@@ -317,6 +328,7 @@ int ptrt_create(int lattice, int nx, int ny, int nz, double tau_plus, double Lam
     if (force)
         for (int a = 0; a < 3; ++a) c->g[a] = force[a];
     if (lattice == PTRT_D2Q9) c->g[2] = 0.0;
+    c->row_kernel = c->ny <= 65535 && c->nz <= 65535;
     if (solid_mask) {
         c->h_mask.assign(solid_mask, solid_mask + c->N);
         for (auto &v : c->h_mask) v = v ? 1 : 0;
@@ -333,6 +345,24 @@ int ptrt_set_storage(ptrt_ctx *c, int storage)
     if (storage_bytes(storage) == 0) return fail(c, PTRT_EINVAL, "unknown storage type");
     if (c->allocated) return fail(c, PTRT_ESTATE, "storage can only change before the first init");
     c->storage = storage;
+    return PTRT_OK;
+}
+
+int ptrt_set_model(ptrt_ctx *c, int model)
+{
+    if (!c) return PTRT_EINVAL;
+    if (model != MODEL_PTRT && model != MODEL_TRT_RLB && model != MODEL_TRT)
+        return fail(c, PTRT_EINVAL, "unknown collision model");
+    if (model != MODEL_PTRT && !c->row_kernel)
+        return fail(c, PTRT_EINVAL, "comparison models need ny and nz <= 65535");
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
+    c->model = model;
+    for (auto &gx : c->graph)
+        if (gx) {
+            hipGraphExecDestroy(gx);
+            gx = nullptr;
+        }
     return PTRT_OK;
 }
 

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptrt.so"
 
 PTRT_D2Q9, PTRT_D3Q19 = 0, 1
 PTRT_F64, PTRT_F32, PTRT_F16, PTRT_BF16 = 0, 1, 2, 3
+PTRT_MODEL_PTRT, PTRT_MODEL_TRT_RLB, PTRT_MODEL_TRT = 0, 1, 2
+MODEL = {"ptrt": PTRT_MODEL_PTRT, "trt-rlb": PTRT_MODEL_TRT_RLB, "trt": PTRT_MODEL_TRT}
 STORAGE = {"f64": PTRT_F64, "f32": PTRT_F32, "f16": PTRT_F16, "bf16": PTRT_BF16}
 Q_OF = {PTRT_D2Q9: 9, PTRT_D3Q19: 19}
 
@@ -54,6 +56,7 @@ _SIGS = {
                                    ctypes.c_double, ctypes.c_double, _dp, _u8p,
                                    ctypes.POINTER(_vp)]),
     "ptrt_set_storage": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_set_model": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ptrt_init_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
     "ptrt_step": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -154,6 +157,11 @@ def ptrt_set_storage(h, storage):
     return _check(_lib.ptrt_set_storage(h.ptr, storage), h.ptr)
 
 
+def ptrt_set_model(h, model):
+    model = MODEL.get(model, model)
+    return _check(_lib.ptrt_set_model(h.ptr, model), h.ptr)
+
+
 def ptrt_set_stream(h, stream):
     return _check(_lib.ptrt_set_stream(h.ptr, _stream_handle(stream)), h.ptr)
 
@@ -235,10 +243,12 @@ class Lattice:
     """Convenience owner of one handle: create / init / step / read back."""
 
     def __init__(self, lattice, nx, ny, nz, tau_plus, Lambda, force=None, solid_mask=None,
-                 storage="f32", stream=None):
+                 storage="f32", stream=None, model="ptrt"):
         self.h = ptrt_create(lattice, nx, ny, nz, tau_plus, Lambda, force, solid_mask)
         try:
             ptrt_set_storage(self.h, storage)
+            if model != "ptrt":
+                ptrt_set_model(self.h, model)
             if stream is not None:
                 ptrt_set_stream(self.h, stream)
         except Exception:

@@ -219,3 +219,29 @@ def test_force_terms_reading_matches_trt_rlb_not_literal():
     assert np.abs(gain - F).max() < 1e-16 * 4
     literal_gain = F * (1.5 - 1 / (2 * tp))
     assert np.abs(gain - literal_gain).min() > 1e-5
+
+
+@pytest.mark.parametrize("lat,name,D", LATS)
+def test_oracle_trt_spectrum_and_ptrt_difference(lat, name, D):
+    """The oracle's standard-TRT comparison model: its linearised collision has
+    the ghost eigenvalue 1 - 1/tau+ (Eq. collision_TRT), it differs from
+    P-TRT exactly by the ghost projection relaxed with tau+, and it coincides
+    with P-TRT at tau+ = 1."""
+    spec = golden("collision_spectrum.json")[name]
+    e, w, opp = O.lattice(lat)
+    phi, nrm = O.ghost_basis(lat)
+    tp, tm = 0.8, 2.5
+    J = _jacobian(lambda x: O.collide_trt(lat, x[None], None, tp, tm)[0], w.copy())
+    ev = np.sort(np.linalg.eigvals(J).real)
+    assert _count(ev, 1 - 1 / tp) == spec["a_plus"] + spec["ghost"]
+    assert _count(ev, 0.0) == 0
+    f = _states(lat, 100, seed=81 + D, amp=0.1)
+    g = np.array([1e-3, -5e-4, 2e-4])
+    g[D:] = 0
+    a = O.collide(lat, f, g, tp, tau_minus=tm)
+    b = O.collide_trt(lat, f, g, tp, tm)
+    rho, u = O.node_moments(lat, f, g)
+    fneq = f - O.equilibrium(lat, rho, u)
+    pg = sum(w[None] * phi[k][None] / nrm[k] * (fneq @ phi[k])[:, None] for k in range(len(nrm)))
+    assert np.abs((b - a) - (1 - 1 / tp) * pg).max() < 1e-15
+    assert np.abs(O.collide_trt(lat, f, g, 1.0, tm) - O.collide(lat, f, g, 1.0, tau_minus=tm)).max() < 1e-15
