@@ -37,6 +37,8 @@
  *   D3Q19 (App. A.2; order and weights 1/3, 1/18, 1/36 chosen here):
  *         rest; +x -x +y -y +z -z; (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0);
  *         (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1); (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *   D3Q27 (App. A.3; weights 8/27, 2/27, 1/54, 1/216): the D3Q19 order, then
+ *         (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1)
  *
  * Time: the state is "populations at integer time t, before collision".
  * ptrt_init_equilibrium sets f(t=0) = f^eq(rho, u) and t = 0; ptrt_step(n)
@@ -70,7 +72,7 @@ extern "C" {
 typedef struct ptrt_ctx ptrt_ctx;
 typedef struct ptrt_batch ptrt_batch;
 
-enum ptrt_lattice { PTRT_D2Q9 = 0, PTRT_D3Q19 = 1 };
+enum ptrt_lattice { PTRT_D2Q9 = 0, PTRT_D3Q19 = 1, PTRT_D3Q27 = 2 };
 
 enum ptrt_storage { PTRT_F64 = 0, PTRT_F32 = 1, PTRT_F16 = 2, PTRT_BF16 = 3 };
 
@@ -81,8 +83,19 @@ enum ptrt_storage { PTRT_F64 = 0, PTRT_F32 = 1, PTRT_F16 = 2, PTRT_BF16 = 3 };
  * reconstruction is the orthogonal projection onto the third-order modes)
  * or standard TRT (P-TRT without the ghost subtraction: the ghost modes
  * relax with tau+, Eq. collision_TRT).  All three share the state layout,
- * the streaming and the force convention. */
-enum ptrt_model { PTRT_MODEL_PTRT = 0, PTRT_MODEL_TRT_RLB = 1, PTRT_MODEL_TRT = 2 };
+ * the streaming and the force convention.
+ *
+ * On D3Q27 P-TRT is the paper's hybrid (Eq. PTRT_D3Q27): R2 by the Hermite
+ * stress projection, R3 by the antisymmetric part, which keeps the three
+ * fifth-order antisymmetric modes; PTRT_MODEL_PTRT_EXACT projects those out
+ * as well (App. A.3), which equals TRT-RLB.  On D2Q9 and D3Q19
+ * PTRT_MODEL_PTRT_EXACT is the same as PTRT_MODEL_PTRT. */
+enum ptrt_model {
+    PTRT_MODEL_PTRT = 0,
+    PTRT_MODEL_TRT_RLB = 1,
+    PTRT_MODEL_TRT = 2,
+    PTRT_MODEL_PTRT_EXACT = 3
+};
 
 enum ptrt_status {
     PTRT_OK = 0,

@@ -14,8 +14,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libptrt_oracle.so")
 
-D2Q9, D3Q19 = 0, 1
-_Q = {D2Q9: 9, D3Q19: 19}
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
+_Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
+
+# collision models of the oracle
+PTRT, TRT, PTRT_EXACT, PTRT_GHOST = 0, 2, 3, 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -53,6 +56,9 @@ def _load():
                                                  _dp, _u8p, _dp, ctypes.c_int, _llp, _dp]
         lib.ptrt_oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _u8p,
                                                 _dp, _dp]
+        lib.ptrt_oracle_collide_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                                  _dp, ctypes.c_double, ctypes.c_double, _dp]
+        lib.ptrt_oracle_fifth_modes.argtypes = [ctypes.c_int, _dp]
         lib.ptrt_oracle_max_threads.argtypes = []
         _lib = lib
     return _lib
@@ -87,8 +93,8 @@ def lattice(lat):
 def ghost_basis(lat):
     """Orthogonal ghost basis phi [NG,Q] and its weighted norms [NG]."""
     Q = _Q[lat]
-    phi = np.zeros((3, Q))
-    nrm = np.zeros(3)
+    phi = np.zeros((7, Q))
+    nrm = np.zeros(7)
     ng = _load().ptrt_oracle_ghost_basis(lat, _p(phi), _p(nrm))
     return phi[:ng].copy(), nrm[:ng].copy()
 
@@ -126,6 +132,25 @@ def collide_trt(lat, f, g, tau_plus, tau_minus):
     return out
 
 
+def collide_model(lat, model, f, g, tau_plus, tau_minus):
+    """Collision of independent nodes with an oracle model (PTRT, TRT,
+    PTRT_EXACT, PTRT_GHOST), [n,Q] -> [n,Q]."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
+    out = np.zeros_like(f)
+    rc = _load().ptrt_oracle_collide_model(lat, int(model), f.shape[0], _p(f), _p(_g3(g)),
+                                           tau_plus, tau_minus, _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle collide_model failed ({rc})")
+    return out
+
+
+def fifth_modes(lat=D3Q27):
+    """psi^(5,k) of D3Q27 as rows [3,27] (App. A.3)."""
+    psi = np.zeros((3, 27))
+    assert _load().ptrt_oracle_fifth_modes(lat, _p(psi)) == 3
+    return psi
+
+
 def node_moments(lat, f, g=None):
     """rho [n], u [n,3] of independent nodes f [n,Q] (Eq. macro)."""
     f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
@@ -146,7 +171,7 @@ class Lattice:
     def __init__(self, lat, nx, ny, nz, tau_plus, Lambda, g=None, solid=None,
                  tau_minus=None, nthreads=0, model=0):
         self.lat = lat
-        self.model = int(model)  # 0: P-TRT, 2: standard TRT
+        self.model = int(model)  # PTRT, TRT, PTRT_EXACT or PTRT_GHOST
         self.Q = _Q[lat]
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz

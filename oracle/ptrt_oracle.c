@@ -36,6 +36,18 @@
  *  R5 (time step) collide, then stream (left side of Eq. PTRT); halfway
  *     bounce-back sends a population whose target node is solid back into
  *     the opposite direction of its source node (Sec. 3.3).
+ *  R6 (D3Q27, App. A.3).  P-TRT on D3Q27 is the hybrid of Eq. PTRT_D3Q27:
+ *     R2 is the Hermite stress projection w_i H2_i : A2 / (2 c_s^4) of
+ *     f^neq, R3 is f^{neq,-} plus the force correction; the "exact" variant
+ *     also subtracts the projections onto the three fifth-order modes
+ *     psi^(5,k).  The appendix states that those modes are non-zero only on
+ *     the body diagonals; they are also non-zero on the axial and on some
+ *     face-diagonal velocities (psi^(5,x) = 1/9 at e = (1,0,0), -2/9 at
+ *     (1,1,0)), so the projection here sums over every velocity.  The seven
+ *     printed ghost modes are mutually orthogonal and orthogonal to the
+ *     stress modes on D3Q27; they are kept for the Eq. PTRT form of the
+ *     collision (ghost subtraction on D3Q27), which Theorem 2 makes equal to
+ *     the hybrid's R2 and which the tests use as a pin.
  *
  * Population layout used by this file: f[node * Q + i], node = (z*ny+y)*nx+x.
  */
@@ -47,8 +59,8 @@
 #include <omp.h>
 #endif
 
-#define QMAX 19
-#define NGMAX 3
+#define QMAX 27
+#define NGMAX 7
 
 typedef struct {
     int D, Q;
@@ -99,6 +111,25 @@ static void lattice_d3q19(Lattice *L)
             n2 += ev[i][a] * ev[i][a];
         }
         L->w[i] = (n2 == 0) ? 1.0 / 3.0 : (n2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+}
+
+/* D3Q27: the D3Q19 set plus the eight body diagonals (App. A.3), weights
+ * 8/27, 2/27, 1/54, 1/216 (tensor product of the 1D weights 2/3, 1/6). The
+ * first nineteen velocities are in the D3Q19 order; the diagonals follow,
+ * each followed by its opposite. */
+static void lattice_d3q27(Lattice *L)
+{
+    static const int diag[8][3] = {{1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+                                   {1, -1, 1}, {-1, 1, -1},  {-1, 1, 1}, {1, -1, -1}};
+    lattice_d3q19(L);
+    L->Q = 27;
+    for (int k = 0; k < 8; ++k)
+        for (int a = 0; a < 3; ++a) L->e[19 + k][a] = diag[k][a];
+    for (int i = 0; i < 27; ++i) {
+        double w = 1.0;
+        for (int a = 0; a < 3; ++a) w *= L->e[i][a] == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+        L->w[i] = w;
     }
 }
 
@@ -159,14 +190,30 @@ static void build_ghost_basis(Lattice *L)
         }
     int nhydro = nb;
 
-    /* ghost products in the paper's order: (x,y), then (y,z), (z,x) */
+    /* ghost products in the paper's order: (x,y), then (y,z), (z,x); on
+     * D3Q27 then the sixth-order product / c_s^2 and the shear-energy modes
+     * e_x e_y (e_z^2-c_s^2), e_y e_z (e_x^2-c_s^2), e_z e_x (e_y^2-c_s^2) */
     static const int pairs[3][2] = {{0, 1}, {1, 2}, {2, 0}};
-    L->NG = (D == 2) ? 1 : 3;
+    L->NG = (D == 2) ? 1 : (Q == 19 ? 3 : 7);
     for (int k = 0; k < L->NG; ++k) {
-        int a = pairs[k][0], b = pairs[k][1];
-        for (int i = 0; i < Q; ++i)
-            basis[nb][i] = (L->e[i][a] * L->e[i][a] - L->cs2) *
-                           (L->e[i][b] * L->e[i][b] - L->cs2);
+        for (int i = 0; i < Q; ++i) {
+            const int *e = L->e[i];
+            double hx = e[0] * e[0] - L->cs2, hy = e[1] * e[1] - L->cs2, hz = e[2] * e[2] - L->cs2;
+            double v;
+            if (k < 3) {
+                int a = pairs[k][0], b = pairs[k][1];
+                v = (e[a] * e[a] - L->cs2) * (e[b] * e[b] - L->cs2);
+            } else if (k == 3) {
+                v = hx * hy * hz / L->cs2;
+            } else if (k == 4) {
+                v = e[0] * e[1] * hz;
+            } else if (k == 5) {
+                v = e[1] * e[2] * hx;
+            } else {
+                v = e[2] * e[0] * hy;
+            }
+            basis[nb][i] = v;
+        }
         nb++;
     }
 
@@ -191,6 +238,8 @@ static int make_lattice(int id, Lattice *L)
         lattice_d2q9(L);
     else if (id == 1)
         lattice_d3q19(L);
+    else if (id == 2)
+        lattice_d3q27(L);
     else
         return -1;
     L->cs2 = 1.0 / 3.0;
@@ -252,35 +301,94 @@ static void ghost_projection(const Lattice *L, const double *fneq, double *pg)
     }
 }
 
-/* One P-TRT collision, Eq. PTRT with R1: f -> f*.  With ghost == 0 the
- * ghost subtraction is skipped, which is standard TRT (Eq. collision_TRT:
- * the ghost modes relax with tau+ like the stress modes). */
+/* Fifth-order antisymmetric modes of D3Q27 (App. A.3):
+ * psi^(5,x)_i = e_ix (e_iy^2 - c_s^2)(e_iz^2 - c_s^2) and cyclic. */
+static double psi5(const Lattice *L, int k, int i)
+{
+    const int *e = L->e[i];
+    int a = k, b = (k + 1) % 3, c = (k + 2) % 3;
+    return e[a] * (e[b] * e[b] - L->cs2) * (e[c] * e[c] - L->cs2);
+}
+
+/* Collision models of the oracle. */
+enum {
+    MODEL_PTRT = 0,       /* Eq. PTRT; on D3Q27 the hybrid Eq. PTRT_D3Q27 */
+    MODEL_TRT = 2,        /* Eq. collision_TRT: no ghost subtraction */
+    MODEL_PTRT_EXACT = 3, /* D3Q27 hybrid with the fifth-order projection removed */
+    MODEL_PTRT_GHOST = 4  /* Eq. PTRT (ghost subtraction) on every lattice */
+};
+
+/* R2 by the Hermite stress projection, w_i H2_i : A2 / (2 c_s^4) with
+ * A2_ab = sum_j H2_j,ab fneq_j (Eq. projection, Eq. R2R3_hermite). */
+static void stress_projection(const Lattice *L, const double *fneq, double *r2)
+{
+    double A[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            A[a][b] = 0.0;
+            for (int j = 0; j < L->Q; ++j) A[a][b] += hermite2(L, j, a, b) * fneq[j];
+        }
+    for (int i = 0; i < L->Q; ++i) {
+        double c = 0.0;
+        for (int a = 0; a < L->D; ++a)
+            for (int b = 0; b < L->D; ++b) c += hermite2(L, i, a, b) * A[a][b];
+        r2[i] = L->w[i] * c / (2.0 * L->cs2 * L->cs2);
+    }
+}
+
+/* Sum over k of (P^(5,k) f)_i = w_i psi5_ki / N5_k * sum_j psi5_kj f_j. */
+static void fifth_order_projection(const Lattice *L, const double *fneq, double *p5)
+{
+    for (int i = 0; i < L->Q; ++i) p5[i] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double S = 0.0, N = 0.0;
+        for (int j = 0; j < L->Q; ++j) {
+            S += psi5(L, k, j) * fneq[j];
+            N += L->w[j] * psi5(L, k, j) * psi5(L, k, j);
+        }
+        for (int i = 0; i < L->Q; ++i) p5[i] += L->w[i] * psi5(L, k, i) / N * S;
+    }
+}
+
+/* One collision f -> f*, Eq. PTRT with R1 (Eq. PTRT_D3Q27 on D3Q27, R6).
+ * MODEL_TRT skips the ghost subtraction, which is standard TRT (Eq.
+ * collision_TRT: the ghost modes relax with tau+ like the stress modes). */
 static void collide_model(const Lattice *L, const double *f, const double g[3],
-                          double tau_p, double tau_m, int ghost, double *fstar)
+                          double tau_p, double tau_m, int model, double *fstar)
 {
     double rho, u[3], feq[QMAX], fneq[QMAX], plus[QMAX], minus[QMAX], pg[QMAX];
+    double R2[QMAX], p5[QMAX];
+    int q27 = L->Q == 27;
     moments(L, f, g, &rho, u);
     equilibrium(L, rho, u, feq);
     for (int i = 0; i < L->Q; ++i) fneq[i] = f[i] - feq[i];
     parity_split(L, fneq, plus, minus);
-    if (ghost)
-        ghost_projection(L, fneq, pg);
+    if (q27 && (model == MODEL_PTRT || model == MODEL_PTRT_EXACT)) {
+        stress_projection(L, fneq, R2); /* Eq. PTRT_D3Q27 */
+    } else {
+        if (model == MODEL_TRT)
+            for (int i = 0; i < L->Q; ++i) pg[i] = 0.0;
+        else
+            ghost_projection(L, fneq, pg);
+        for (int i = 0; i < L->Q; ++i) R2[i] = plus[i] - pg[i]; /* Theorem 2, Eq. R2_D2Q9 */
+    }
+    if (q27 && model == MODEL_PTRT_EXACT)
+        fifth_order_projection(L, fneq, p5);
     else
-        for (int i = 0; i < L->Q; ++i) pg[i] = 0.0;
+        for (int i = 0; i < L->Q; ++i) p5[i] = 0.0;
     double F[3] = {rho * g[0], rho * g[1], rho * g[2]};
     for (int i = 0; i < L->Q; ++i) {
         double eF = L->e[i][0] * F[0] + L->e[i][1] * F[1] + L->e[i][2] * F[2];
         double half_force = 0.5 * L->w[i] * eF / L->cs2;
-        double R2 = plus[i] - pg[i];           /* Theorem 2, Eq. R2_D2Q9 */
-        double R3 = minus[i] + half_force;     /* Eq. R3_force */
-        fstar[i] = feq[i] + (1.0 - 1.0 / tau_p) * R2 + (1.0 - 1.0 / tau_m) * R3 + half_force;
+        double R3 = minus[i] - p5[i] + half_force; /* Eq. R3_force */
+        fstar[i] = feq[i] + (1.0 - 1.0 / tau_p) * R2[i] + (1.0 - 1.0 / tau_m) * R3 + half_force;
     }
 }
 
 static void collide(const Lattice *L, const double *f, const double g[3], double tau_p,
                     double tau_m, double *fstar)
 {
-    collide_model(L, f, g, tau_p, tau_m, 1, fstar);
+    collide_model(L, f, g, tau_p, tau_m, MODEL_PTRT, fstar);
 }
 
 /* tau_{s,2} from the magic parameter Lambda = (tau+ - 1/2)(tau- - 1/2). */
@@ -379,6 +487,9 @@ int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_
     Lattice L;
     if (make_lattice(id, &L)) return -1;
     if (id == 0 && nz != 1) return -2;
+    if (model != MODEL_PTRT && model != MODEL_TRT && model != MODEL_PTRT_EXACT &&
+        model != MODEL_PTRT_GHOST)
+        return -4;
     double tau_m = tau_minus > 0.0 ? tau_minus : tau_minus_from_lambda(tau_plus, Lambda);
     int Q = L.Q;
     size_t N = (size_t)nx * ny * nz;
@@ -394,7 +505,7 @@ int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_
 #pragma omp parallel for schedule(static)
         for (long long m = 0; m < (long long)N; ++m) {
             if (solid && solid[m]) continue;
-            collide_model(&L, f + m * Q, g, tau_plus, tau_m, model == 0, fstar + m * Q);
+            collide_model(&L, f + m * Q, g, tau_plus, tau_m, model, fstar + m * Q);
         }
         /* streaming, left side of Eq. PTRT, with halfway bounce-back */
 #pragma omp parallel for schedule(static)
@@ -416,7 +527,7 @@ int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_
     return 0;
 }
 
-/* model 0: P-TRT, model 2: standard TRT (no ghost subtraction). */
+/* P-TRT (Eq. PTRT, Eq. PTRT_D3Q27 on D3Q27). */
 int ptrt_oracle_run(int id, int nx, int ny, int nz, double tau_plus, double Lambda,
                     double tau_minus, const double g[3], const uint8_t *solid,
                     double *f, int nsteps, int nthreads)
@@ -432,8 +543,35 @@ int ptrt_oracle_collide_trt(int id, int n, const double *f_in, const double g[3]
     Lattice L;
     if (make_lattice(id, &L)) return -1;
     for (int m = 0; m < n; ++m)
-        collide_model(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_minus, 0, f_out + (size_t)m * L.Q);
+        collide_model(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_minus, MODEL_TRT,
+                      f_out + (size_t)m * L.Q);
     return 0;
+}
+
+/* Collision of n independent nodes with any oracle model (0 P-TRT, 2 TRT,
+ * 3 P-TRT with the fifth-order projection removed, 4 Eq. PTRT ghost form). */
+int ptrt_oracle_collide_model(int id, int model, int n, const double *f_in, const double g[3],
+                              double tau_plus, double tau_minus, double *f_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    if (model != MODEL_PTRT && model != MODEL_TRT && model != MODEL_PTRT_EXACT &&
+        model != MODEL_PTRT_GHOST)
+        return -4;
+    for (int m = 0; m < n; ++m)
+        collide_model(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_minus, model,
+                      f_out + (size_t)m * L.Q);
+    return 0;
+}
+
+/* Fifth-order modes psi^(5,k) of D3Q27 [3][27]; returns 3 (or -1). */
+int ptrt_oracle_fifth_modes(int id, double *psi_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L) || L.Q != 27) return -1;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < L.Q; ++i) psi_out[k * L.Q + i] = psi5(&L, k, i);
+    return 3;
 }
 
 /*

@@ -21,6 +21,9 @@ Readings (the same as the C oracle's where they overlap):
   their span, R3_i = w_i sum_kl H_ki (G^-1)_kl A_l with the Gram matrix
   G_kl = sum_i w_i H_ki H_li.  On D2Q9 that equals the printed formula
   (checked by a test).
+* D3Q27 (App. A.3) has seven third-order modes (the six H_aab and H_xyz);
+  they are mutually orthogonal there, so the printed contraction is the
+  projection, as on D2Q9 (checked by a test).
 """
 import itertools
 
@@ -56,8 +59,20 @@ def d3q19():
     return e, w
 
 
+def d3q27():
+    """D3Q27 (App. A.3): every velocity with components in {-1, 0, 1}; the
+    D3Q19 order, then the body diagonals, each followed by its opposite;
+    weights are products of the 1D weights 2/3 (0) and 1/6 (+-1)."""
+    e19, _ = d3q19()
+    diag = [(1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
+            (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
+    e = np.vstack([e19, np.array(diag, dtype=np.float64)])
+    w = np.prod(np.where(e == 0, 2 / 3, 1 / 6), axis=1)
+    return e, w
+
+
 def lattice(name):
-    return d2q9() if name == "D2Q9" else d3q19()
+    return {"D2Q9": d2q9, "D3Q19": d3q19, "D3Q27": d3q27}[name]()
 
 
 def opposite(e):
@@ -90,12 +105,15 @@ def equilibrium(e, w, rho, u):
 
 
 def third_order_modes(e):
-    """The independent third-order polynomials H_aab (a != b) as rows [M,Q]."""
+    """The independent third-order polynomials H_aab (a != b) and, where the
+    lattice supports it (not identically zero), H_xyz, as rows [M,Q]."""
     H3 = hermite3(e)
     D = e.shape[1]
     rows = []
     for a, b in itertools.permutations(range(D), 2):
         rows.append(H3[:, a, a, b])
+    if D == 3 and np.any(H3[:, 0, 1, 2] != 0):
+        rows.append(H3[:, 0, 1, 2])
     return np.array(rows)
 
 
@@ -118,8 +136,8 @@ def collide(lattice_name, f, g, tau_plus, tau_minus, third="auto"):
     """TRT-RLB post-collision state, f [n,Q] -> [n,Q] (Eq. TRT-RLB).
 
     g is the body acceleration (F = rho g).  ``third`` selects the third-order
-    reconstruction: "literal", "projection" or "auto" (literal on D2Q9,
-    projection on D3Q19)."""
+    reconstruction: "literal", "projection" or "auto" (literal on D2Q9 and
+    D3Q27, projection on D3Q19)."""
     e, w = lattice(lattice_name)
     D = e.shape[1]
     g = np.zeros(D) if g is None else np.asarray(g, dtype=np.float64)[:D]
@@ -133,7 +151,7 @@ def collide(lattice_name, f, g, tau_plus, tau_minus, third="auto"):
     A2 = np.einsum("iab,ni->nab", H2, fneq)                  # Eq. projection
     R2 = w[None] * np.einsum("iab,nab->ni", H2, A2) / (2 * CS2 ** 2)
     if third == "auto":
-        third = "literal" if lattice_name == "D2Q9" else "projection"
+        third = "projection" if lattice_name == "D3Q19" else "literal"
     R3 = (reconstruct_third_literal if third == "literal" else reconstruct_third_projection)(e, w, fneq)
     P1 = w[None] * ((fneq @ e) @ e.T) / CS2                  # first-order part
     S = (1 - 1 / (2 * tau_plus)) * w[None] * (F @ e.T) / CS2  # Scheme II, G_i = 0

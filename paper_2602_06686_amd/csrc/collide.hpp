@@ -201,18 +201,143 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
 
     const C eq0 = C(L::w(0)) * (drho + rho * m15uu);
     h[0] = eq0 + r.ap * ((h[0] - eq0) - pg0);
-    const C wr[2] = {C(L::w(L::pair_first(0))) * rho, C(L::w(L::pair_first(L::NP - 1))) * rho};
     static_for<L::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int i = L::pair_first(p), j = L::opp(i);
-        constexpr int cls = L::pair_class(p);
         const C w = C(L::w(i));
         const C eu = edot<L, i>(ux, uy, uz);
         const C eu2 = eu * eu;
         const C eqp = w * (drho + rho * (C(4.5) * eu2 + m15uu));
         const C sym = eqp + r.ap * ((C(0.5) * sp[p] - eqp) - pg[p]);
-        const C eqm = wr[cls] * (eu * (C(3) + C(4.5) * (eu2 - uu)));
+        const C eqm = (w * rho) * (eu * (C(3) + C(4.5) * (eu2 - uu)));
         const C anti = eqm + r.am * (C(0.5) * dp[p] - eqm) + rho * r.K[p];
+        h[i] = sym + anti;
+        h[j] = sym - anti;
+    });
+    rho_o = rho;
+    ux_o = ux;
+    uy_o = uy;
+    uz_o = uz;
+}
+
+// Hybrid P-TRT on D3Q27 (Eq. PTRT_D3Q27, App. A.3): there are more ghost
+// modes (7) than stress modes (6), so R2 is the Hermite stress projection
+// itself, R2_i = w_i H2_i : A2 / (2 c_s^4) with A2_ab = sum_j H2_j,ab fneq_j;
+// R3 = f^neq,- + (3/2) w_i e_i.F.  With EXACT the three fifth-order
+// antisymmetric modes psi_a = e_a (e_b^2 - c_s^2)(e_c^2 - c_s^2) are
+// projected out of f^neq,- first (weighted norm 4/243 each), which makes the
+// update equal to TRT-RLB on this lattice.
+template <class C, bool EXACT>
+__device__ __forceinline__ void collide_d3q27(C (&h)[27], const Coef<D3Q27, C> &r, C &rho_o,
+                                              C &ux_o, C &uy_o, C &uz_o)
+{
+    using L = D3Q27;
+    C sp[L::NP], dp[L::NP];
+    static_for<L::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = L::pair_first(p), j = L::opp(i);
+        sp[p] = h[i] + h[j];
+        dp[p] = h[i] - h[j];
+    });
+    C drho = h[0], jx = C(0), jy = C(0), jz = C(0);
+    static_for<L::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = L::pair_first(p);
+        drho += sp[p];
+        if constexpr (L::ex(i) == 1) jx += dp[p];
+        if constexpr (L::ex(i) == -1) jx -= dp[p];
+        if constexpr (L::ey(i) == 1) jy += dp[p];
+        if constexpr (L::ey(i) == -1) jy -= dp[p];
+        if constexpr (L::ez(i) == 1) jz += dp[p];
+        if constexpr (L::ez(i) == -1) jz -= dp[p];
+    });
+    const C rho = C(1) + drho;
+    const C inv = C(1) / rho;
+    const C ux = jx * inv + r.hgx;
+    const C uy = jy * inv + r.hgy;
+    const C uz = jz * inv + r.hgz;
+    const C uu = ux * ux + uy * uy + uz * uz;
+    const C m15uu = C(-1.5) * uu;
+
+    // parity halves of the equilibrium and of the non-equilibrium part
+    C eqp[L::NP], eqm[L::NP], np[L::NP], nm[L::NP];
+    static_for<L::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = L::pair_first(p);
+        const C w = C(L::w(i));
+        const C eu = edot<L, i>(ux, uy, uz);
+        const C eu2 = eu * eu;
+        eqp[p] = w * (drho + rho * (C(4.5) * eu2 + m15uu));
+        eqm[p] = (w * rho) * (eu * (C(3) + C(4.5) * (eu2 - uu)));
+        np[p] = C(0.5) * sp[p] - eqp[p];
+        nm[p] = C(0.5) * dp[p] - eqm[p];
+    });
+    const C eq0 = C(L::w(0)) * (drho + rho * m15uu);
+    const C n0 = h[0] - eq0;
+
+    // second-order Hermite moments of f^neq (only the symmetric part counts)
+    constexpr double third = 1.0 / 3.0;
+    C Axx = C(-third) * n0, Ayy = C(-third) * n0, Azz = C(-third) * n0;
+    C Axy = C(0), Axz = C(0), Ayz = C(0);
+    static_for<L::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = L::pair_first(p);
+        constexpr double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+        const C t = C(2) * np[p];
+        Axx += C(ex * ex - third) * t;
+        Ayy += C(ey * ey - third) * t;
+        Azz += C(ez * ez - third) * t;
+        if constexpr (ex * ey != 0) Axy += C(ex * ey) * t;
+        if constexpr (ex * ez != 0) Axz += C(ex * ez) * t;
+        if constexpr (ey * ez != 0) Ayz += C(ey * ez) * t;
+    });
+
+    // fifth-order antisymmetric moments (EXACT only)
+    C S5x = C(0), S5y = C(0), S5z = C(0);
+    if constexpr (EXACT) {
+        static_for<L::NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int i = L::pair_first(p);
+            constexpr double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+            constexpr double px = ex * (ey * ey - third) * (ez * ez - third);
+            constexpr double py = ey * (ez * ez - third) * (ex * ex - third);
+            constexpr double pz = ez * (ex * ex - third) * (ey * ey - third);
+            const C t = C(2) * nm[p];
+            if constexpr (px != 0) S5x += C(px) * t;
+            if constexpr (py != 0) S5y += C(py) * t;
+            if constexpr (pz != 0) S5z += C(pz) * t;
+        });
+        const C inv_norm = C(243.0 / 4.0);
+        S5x *= inv_norm;
+        S5y *= inv_norm;
+        S5z *= inv_norm;
+    }
+
+    h[0] = eq0 + r.ap * (C(L::w(0) * 4.5 * -third) * (Axx + Ayy + Azz));
+    static_for<L::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = L::pair_first(p), j = L::opp(i);
+        constexpr double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+        constexpr double w = L::w(i);
+        // R2 = w (9/2) H2 : A2, off-diagonal components counted twice
+        C r2 = C(ex * ex - third) * Axx + C(ey * ey - third) * Ayy + C(ez * ez - third) * Azz;
+        if constexpr (ex * ey != 0) r2 += C(2 * ex * ey) * Axy;
+        if constexpr (ex * ez != 0) r2 += C(2 * ex * ez) * Axz;
+        if constexpr (ey * ez != 0) r2 += C(2 * ey * ez) * Ayz;
+        const C R2 = C(4.5 * w) * r2;
+        C R3 = nm[p];
+        if constexpr (EXACT) {
+            constexpr double px = ex * (ey * ey - third) * (ez * ez - third);
+            constexpr double py = ey * (ez * ez - third) * (ex * ex - third);
+            constexpr double pz = ez * (ex * ex - third) * (ey * ey - third);
+            C p5 = C(0);
+            if constexpr (px != 0) p5 += C(w * px) * S5x;
+            if constexpr (py != 0) p5 += C(w * py) * S5y;
+            if constexpr (pz != 0) p5 += C(w * pz) * S5z;
+            R3 = R3 - p5;
+        }
+        const C sym = eqp[p] + r.ap * R2;
+        const C anti = eqm[p] + r.am * R3 + rho * r.K[p];
         h[i] = sym + anti;
         h[j] = sym - anti;
     });

@@ -38,6 +38,7 @@ inline int dispatch(int lattice, int storage, bool mask, F &&f)
     };
     if (lattice == PTRT_D2Q9) return with_lat(Tag<D2Q9>{});
     if (lattice == PTRT_D3Q19) return with_lat(Tag<D3Q19>{});
+    if (lattice == PTRT_D3Q27) return with_lat(Tag<D3Q27>{});
     return PTRT_EINVAL;
 }
 
@@ -54,7 +55,7 @@ inline size_t storage_bytes(int storage)
 
 inline int lattice_q(int lattice)
 {
-    return lattice == PTRT_D2Q9 ? 9 : (lattice == PTRT_D3Q19 ? 19 : 0);
+    return lattice == PTRT_D2Q9 ? 9 : (lattice == PTRT_D3Q19 ? 19 : (lattice == PTRT_D3Q27 ? 27 : 0));
 }
 
 inline bool finite(double v) { return std::isfinite(v); }
@@ -64,7 +65,7 @@ inline bool finite(double v) { return std::isfinite(v); }
 inline int check_params(int lattice, int nx, int ny, int nz, double tau_plus, double Lambda,
                         const double *force, std::string &msg)
 {
-    if (lattice != PTRT_D2Q9 && lattice != PTRT_D3Q19) {
+    if (lattice != PTRT_D2Q9 && lattice != PTRT_D3Q19 && lattice != PTRT_D3Q27) {
         msg = "unknown lattice id " + std::to_string(lattice);
         return PTRT_EINVAL;
     }

@@ -164,7 +164,9 @@ __device__ __forceinline__ unsigned flat_block()
 
 // Collision models: P-TRT (the method), and for comparison TRT-RLB (Hermite
 // projection, Eq. TRT-RLB) and standard TRT (ghost modes kept).
-enum { MODEL_PTRT = 0, MODEL_TRT_RLB = 1, MODEL_TRT = 2 };
+// MODEL_PTRT_EXACT differs from MODEL_PTRT only on D3Q27 (fifth-order
+// antisymmetric modes projected out, App. A.3).
+enum { MODEL_PTRT = 0, MODEL_TRT_RLB = 1, MODEL_TRT = 2, MODEL_PTRT_EXACT = 3 };
 
 // ---------------------------------------------------------------------------
 // One node update: pull, moments, equilibrium, parity split, ghost removal,
@@ -181,8 +183,12 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
     C rho, ux, uy, uz;
     if constexpr (MODEL == MODEL_TRT_RLB)
         collide_trt_rlb<L, C>(h, r, rho, ux, uy, uz);
+    else if constexpr (MODEL == MODEL_TRT)
+        collide<L, C, false>(h, r, rho, ux, uy, uz);
+    else if constexpr (L::Q == 27)
+        collide_d3q27<C, MODEL == MODEL_PTRT_EXACT>(h, r, rho, ux, uy, uz);
     else
-        collide<L, C, MODEL == MODEL_PTRT>(h, r, rho, ux, uy, uz);
+        collide<L, C, true>(h, r, rho, ux, uy, uz);
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);
@@ -203,8 +209,12 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
 // NT: non-temporal stores (the state is far larger than the caches).
 // DIAG: also reduce mass and kinetic energy of the pulled (pre-collision)
 // state into per-block FP64 partials.
+// Workgroups: at most 1024 threads (batch per-lattice launches), except
+// D3Q27 in FP64, launched with at most 256 (row workgroups of 1 KB per
+// direction, or the 64 x 4 fallback): the smaller bound lifts the register
+// cap from 128 to 512 so that its 27 FP64 populations do not spill.
 template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG, int MODEL = MODEL_PTRT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__((L::Q == 27 && sizeof(S) == 8) ? 256 : 1024)
 k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
        const uint8_t *__restrict__ near, Geom g, Coef<L, typename Codec<S>::compute> r,
        double2 *__restrict__ partials)

@@ -84,4 +84,39 @@ struct D3Q19 {
     }
 };
 
+// D3Q27 (App. A.3): the D3Q19 set followed by the eight body diagonals
+// (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1).
+// Weights 8/27, 2/27, 1/54, 1/216.  Pair classes: 0 axial, 1 face, 2 body.
+struct D3Q27 {
+    static constexpr int Q = 27, D = 3, NP = 13;
+    __host__ __device__ static constexpr int ex(int i)
+    {
+        constexpr int t[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                               1, -1, 1, -1, 1, -1, -1, 1};
+        return t[i];
+    }
+    __host__ __device__ static constexpr int ey(int i)
+    {
+        constexpr int t[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                               1, -1, 1, -1, -1, 1, 1, -1};
+        return t[i];
+    }
+    __host__ __device__ static constexpr int ez(int i)
+    {
+        constexpr int t[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                               1, -1, -1, 1, 1, -1, 1, -1};
+        return t[i];
+    }
+    __host__ __device__ static constexpr int opp(int i)
+    {
+        return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);
+    }
+    __host__ __device__ static constexpr int pair_first(int p) { return 2 * p + 1; }
+    __host__ __device__ static constexpr int pair_class(int p) { return p < 3 ? 0 : (p < 9 ? 1 : 2); }
+    __host__ __device__ static constexpr double w(int i)
+    {
+        return i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+};
+
 } // namespace ptrt

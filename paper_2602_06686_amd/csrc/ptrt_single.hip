@@ -254,6 +254,7 @@ void launch_step(ptrt_ctx *c, hipStream_t s)
         using P0 = std::integral_constant<int, MODEL_PTRT>;
         using P1 = std::integral_constant<int, MODEL_TRT_RLB>;
         using P2 = std::integral_constant<int, MODEL_TRT>;
+        using P3 = std::integral_constant<int, MODEL_PTRT_EXACT>;
         auto with_nt = [&](auto rowc, auto mc) {
             if (c->nt_store) go(rowc, std::true_type{}, mc);
             else go(rowc, std::false_type{}, mc);
@@ -264,6 +265,10 @@ void launch_step(ptrt_ctx *c, hipStream_t s)
             with_nt(std::true_type{}, P1{});
         } else if (c->model == MODEL_TRT) {
             with_nt(std::true_type{}, P2{});
+        } else if (c->model == MODEL_PTRT_EXACT) {
+            // the fifth-order modes exist on D3Q27 only; elsewhere it is P-TRT
+            if constexpr (L::Q == 27) with_nt(std::true_type{}, P3{});
+            else with_nt(std::true_type{}, P0{});
         } else {
             with_nt(std::true_type{}, P0{});
         }
@@ -351,7 +356,8 @@ int ptrt_set_storage(ptrt_ctx *c, int storage)
 int ptrt_set_model(ptrt_ctx *c, int model)
 {
     if (!c) return PTRT_EINVAL;
-    if (model != MODEL_PTRT && model != MODEL_TRT_RLB && model != MODEL_TRT)
+    if (model != MODEL_PTRT && model != MODEL_TRT_RLB && model != MODEL_TRT &&
+        model != MODEL_PTRT_EXACT)
         return fail(c, PTRT_EINVAL, "unknown collision model");
     if (model != MODEL_PTRT && !c->row_kernel)
         return fail(c, PTRT_EINVAL, "comparison models need ny and nz <= 65535");
@@ -505,6 +511,7 @@ int ptrt_velocity_set(int lattice, int *e_out, double *w_out)
     };
     if (lattice == PTRT_D2Q9) return fill(Tag<D2Q9>{});
     if (lattice == PTRT_D3Q19) return fill(Tag<D3Q19>{});
+    if (lattice == PTRT_D3Q27) return fill(Tag<D3Q27>{});
     return PTRT_EINVAL;
 }
 

@@ -14,7 +14,9 @@
 //          projection onto the span of the third-order modes (the printed
 //          contraction is not a projection there: <H_xxy, H_yzz>_w = -c_s^6),
 //          i.e. per pair (H_a, H_b) of overlapping modes the Gram inverse
-//          9 [[2, 1], [1, 2]] (c_s^6 = 1/27).
+//          9 [[2, 1], [1, 2]] (c_s^6 = 1/27); D3Q27, the printed contraction
+//          (seven mutually orthogonal modes on this tensor-product lattice,
+//          H_xyz counted with its six orderings).
 #pragma once
 
 #include "collide.hpp"
@@ -32,6 +34,7 @@ struct Herm {
     static constexpr double xxy = ey * (ex * ex - third), xyy = ex * (ey * ey - third);
     static constexpr double xxz = ez * (ex * ex - third), yyz = ez * (ey * ey - third);
     static constexpr double xzz = ex * (ez * ez - third), yzz = ey * (ez * ez - third);
+    static constexpr double xyz = ex * ey * ez;
 };
 
 template <class L, class C>
@@ -59,7 +62,7 @@ __device__ __forceinline__ void collide_trt_rlb(C (&h)[L::Q], const Coef<L, C> &
 
     // Hermite moments of the non-equilibrium part (Eq. projection)
     C Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
-    C Bxxy = 0, Bxyy = 0, Bxxz = 0, Byyz = 0, Bxzz = 0, Byzz = 0;
+    C Bxxy = 0, Bxyy = 0, Bxxz = 0, Byyz = 0, Bxzz = 0, Byzz = 0, Bxyz = 0;
     C Jx = 0, Jy = 0, Jz = 0;
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -81,6 +84,7 @@ __device__ __forceinline__ void collide_trt_rlb(C (&h)[L::Q], const Coef<L, C> &
             Bxzz += C(H::xzz) * f;
             Byzz += C(H::yzz) * f;
             Jz += C(H::ez) * f;
+            if constexpr (L::Q == 27) Bxyz += C(H::xyz) * f;
         }
     });
 
@@ -91,7 +95,13 @@ __device__ __forceinline__ void collide_trt_rlb(C (&h)[L::Q], const Coef<L, C> &
         const C w = C(L::w(i));
         C r2 = C(H::xx) * Axx + C(H::yy) * Ayy + C(2.0 * H::xy) * Axy;
         C r3, p1 = C(H::ex) * Jx + C(H::ey) * Jy;
-        if constexpr (L::D == 3) {
+        if constexpr (L::Q == 27) {
+            r2 += C(H::zz) * Azz + C(2.0 * H::xz) * Axz + C(2.0 * H::yz) * Ayz;
+            p1 += C(H::ez) * Jz;
+            r3 = C(13.5) * (C(H::xxy) * Bxxy + C(H::xyy) * Bxyy + C(H::xxz) * Bxxz +
+                            C(H::yyz) * Byyz + C(H::xzz) * Bxzz + C(H::yzz) * Byzz) +
+                 C(27.0 * H::xyz) * Bxyz;
+        } else if constexpr (L::D == 3) {
             r2 += C(H::zz) * Azz + C(2.0 * H::xz) * Axz + C(2.0 * H::yz) * Ayz;
             p1 += C(H::ez) * Jz;
             // Gram-inverse projection per overlapping pair (xxy, yzz), (xxz, yyz), (xyy, xzz)

@@ -19,12 +19,13 @@ import torch  # noqa: F401  (must precede loading libptrt.so, see above)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptrt.so")
 
-PTRT_D2Q9, PTRT_D3Q19 = 0, 1
+PTRT_D2Q9, PTRT_D3Q19, PTRT_D3Q27 = 0, 1, 2
 PTRT_F64, PTRT_F32, PTRT_F16, PTRT_BF16 = 0, 1, 2, 3
-PTRT_MODEL_PTRT, PTRT_MODEL_TRT_RLB, PTRT_MODEL_TRT = 0, 1, 2
-MODEL = {"ptrt": PTRT_MODEL_PTRT, "trt-rlb": PTRT_MODEL_TRT_RLB, "trt": PTRT_MODEL_TRT}
+PTRT_MODEL_PTRT, PTRT_MODEL_TRT_RLB, PTRT_MODEL_TRT, PTRT_MODEL_PTRT_EXACT = 0, 1, 2, 3
+MODEL = {"ptrt": PTRT_MODEL_PTRT, "trt-rlb": PTRT_MODEL_TRT_RLB, "trt": PTRT_MODEL_TRT,
+         "ptrt-exact": PTRT_MODEL_PTRT_EXACT}
 STORAGE = {"f64": PTRT_F64, "f32": PTRT_F32, "f16": PTRT_F16, "bf16": PTRT_BF16}
-Q_OF = {PTRT_D2Q9: 9, PTRT_D3Q19: 19}
+Q_OF = {PTRT_D2Q9: 9, PTRT_D3Q19: 19, PTRT_D3Q27: 27}
 
 STATUS = {0: "PTRT_OK", -1: "PTRT_EINVAL", -2: "PTRT_ETAU", -3: "PTRT_ENOMEM",
           -4: "PTRT_EDEVICE", -5: "PTRT_EDIVERGED", -6: "PTRT_ESTATE"}
@@ -226,6 +227,8 @@ def ptrt_destroy(h):
 
 
 def ptrt_velocity_set(lattice):
+    if lattice not in Q_OF:
+        raise PtrtError(-1, f"unknown lattice {lattice}")
     Q = Q_OF[lattice]
     e = np.zeros((Q, 3), dtype=np.intc)
     w = np.zeros(Q)

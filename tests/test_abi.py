@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert sorted(P.EXPORTED) == declared
 
 
-@pytest.mark.parametrize("lat", [0, 1])
+@pytest.mark.parametrize("lat", [0, 1, 2])
 def test_velocity_tables_match_oracle(lat):
     e, w = P.ptrt_velocity_set(lat)
     eo, wo, _ = O.lattice(lat)
@@ -42,7 +42,7 @@ def test_velocity_set_rejects_unknown_lattice():
 
 
 @pytest.mark.parametrize("args,code", [
-    ((2, 8, 8, 1, 0.6, 0.25), -1),        # unknown lattice
+    ((3, 8, 8, 1, 0.6, 0.25), -1),        # unknown lattice
     ((0, 8, 8, 2, 0.6, 0.25), -1),        # D2Q9 with nz != 1
     ((1, 0, 8, 8, 0.6, 0.25), -1),        # empty lattice
     ((1, 2048, 2048, 1024, 0.6, 0.25), -1),  # 2^32 nodes

@@ -46,7 +46,7 @@ def test_d3q19_composition_and_isotropy():
 
 
 def test_oracle_and_numpy_tables_agree():
-    for lat, name in ((O.D2Q9, "D2Q9"), (O.D3Q19, "D3Q19")):
+    for lat, name in ((O.D2Q9, "D2Q9"), (O.D3Q19, "D3Q19"), (O.D3Q27, "D3Q27")):
         e, w, _ = O.lattice(lat)
         e2, w2 = R.lattice(name)
         D = e2.shape[1]
@@ -73,7 +73,7 @@ def _symmetric_hydro_modes(e, D):
     return np.array(rows, dtype=np.float64)
 
 
-@pytest.mark.parametrize("lat,name", [(O.D2Q9, "D2Q9"), (O.D3Q19, "D3Q19")])
+@pytest.mark.parametrize("lat,name", [(O.D2Q9, "D2Q9"), (O.D3Q19, "D3Q19"), (O.D3Q27, "D3Q27")])
 def test_subspace_dimensions(lat, name):
     """Tables sym_structure / antisym_structure / lattice_summary."""
     g = golden("subspace_structure.json")[name]
@@ -96,10 +96,16 @@ def test_subspace_dimensions(lat, name):
     H1 = e[:, :D].T.astype(float)
     H3 = R.third_order_modes(e[:, :D].astype(float))
     assert np.linalg.matrix_rank(H3) == g["N3"]
-    assert np.linalg.matrix_rank(np.vstack([H1, H3])) == g["dimA"]
+    if g["complete"]:
+        assert np.linalg.matrix_rank(np.vstack([H1, H3])) == g["dimA"]
+    else:
+        # D3Q27: the deficit is filled by the fifth-order modes (App. A.3)
+        assert np.linalg.matrix_rank(np.vstack([H1, H3])) == g["dimA"] - g["deficit"]
+        psi = O.fifth_modes(lat)
+        assert np.linalg.matrix_rank(np.vstack([H1, H3, psi])) == g["dimA"]
 
 
-@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19, O.D3Q27])
 def test_ghost_basis_orthogonal_and_complete(lat):
     """Eq. S_decomp: the ghost basis is symmetric, orthogonal (weighted) to
     the mass and stress modes and to itself, and with them spans S."""
