@@ -7,7 +7,9 @@ on.  The same JSON line carries the other forms of the metric:
 D3Q19 512^3 with FP32 vs FP16 vs BF16 shifted storage, the batched D2Q9
 form (512 uneven lattices, one graph-replayed launch per step, and the
 one-launch-per-lattice comparison), and the two D2Q9 single-lattice
-configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64).
+configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64),
+the collision-model comparison, and D3Q27 (hybrid P-TRT, FP32 / FP16, and
+its comparison models) on the 256^3 vortex.
 
 ``roofline`` describes the dominant kernel (the D3Q19 FP32 step): the
 algorithmic bytes per launch (2 * 19 * 4 bytes per node) over the average
@@ -33,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d3q19_f32_256_traffic.json")
 KERNEL_SOURCES = ["paper_2602_06686_amd/csrc/kernels.hpp", "paper_2602_06686_amd/csrc/collide.hpp",
                   "paper_2602_06686_amd/csrc/codec.hpp", "paper_2602_06686_amd/csrc/lattice.hpp",
-                  "paper_2602_06686_amd/csrc/ptrt_single.hip"]
+                  "paper_2602_06686_amd/csrc/trt_rlb.hpp", "paper_2602_06686_amd/csrc/ptrt_single.hip"]
 
 
 def log(*a):
@@ -188,6 +190,35 @@ def form_models(P, torch, stream, steps, warmup):
     return out
 
 
+def form_d3q27(P, torch, stream, steps, warmup):
+    """D3Q27 (App. A.3) on the 256^3 vortex at 1/tau- = 1.6: the hybrid P-TRT
+    in FP32 and FP16 storage, and the FP32 collision models (exact variant,
+    TRT-RLB, standard TRT) in the same harness."""
+    import lbm_inputs as I
+    n = 256
+    tp = I.tgv3d_params(n)["tau_plus"]
+    lam = I.tau_minus_from_inverse(1.6, tp)
+    rho, u = I.tgv3d(n, 0.05)
+    out = {"workload": "D3Q27 256^3 periodic 3D Taylor-Green vortex (U0=0.05, Re=1600, 1/tau-=1.6)"}
+    for storage, model in (("f32", "ptrt"), ("f16", "ptrt"), ("f32", "ptrt-exact"),
+                           ("f32", "trt-rlb"), ("f32", "trt")):
+        with P.Lattice(P.PTRT_D3Q27, n, n, n, tp, lam, storage=storage, stream=stream,
+                       model=model) as L:
+            L.init_equilibrium(rho, u)
+            ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+            bpn = L.bytes_per_node
+        mps = ms / steps
+        gbs = bpn * n ** 3 / (mps * 1e-3) / 1e9
+        out[f"{model}_{storage}"] = {"ms_per_step": mps, "mlups": n ** 3 / (mps * 1e-3) / 1e6,
+                                     "bytes_per_node": bpn, "achieved_gbs": gbs,
+                                     "hbm_frac": gbs / HBM_PEAK_GBS}
+    base = out["ptrt_f32"]["ms_per_step"]
+    out["fp16_over_fp32"] = out["ptrt_f16"]["mlups"] / out["ptrt_f32"]["mlups"]
+    for m in ("ptrt-exact", "trt-rlb", "trt"):
+        out[f"{m}_time_over_ptrt"] = out[f"{m}_f32"]["ms_per_step"] / base
+    return out
+
+
 def cpu_baseline(n=256, steps=12):
     """The FP64 C oracle, as it is, on `steps` steps of the headline lattice."""
     import lbm_inputs as I
@@ -234,7 +265,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default=None,
-                    help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, models, tgv64")
+                    help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, models, "
+                         "d3q27, tgv64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -280,6 +312,10 @@ def main():
         log("collision models")
         forms["models_fp32"] = form_models(P, torch, stream, max(20, K // 2), max(2, W // 2))
         log(json.dumps(forms["models_fp32"]))
+    if only in (None, "d3q27"):
+        log("D3Q27 256^3")
+        forms["d3q27_256"] = form_d3q27(P, torch, stream, max(20, K // 2), max(2, W // 2))
+        log(json.dumps(forms["d3q27_256"]))
     if only in (None, "tgv64"):
         log("D2Q9 FP64 64^2")
         forms["d2q9_64_f64"] = form_tgv64(P, torch, stream, 1000, 50)

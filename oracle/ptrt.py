@@ -19,6 +19,8 @@ _Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 
 # collision models of the oracle
 PTRT, TRT, PTRT_EXACT, PTRT_GHOST = 0, 2, 3, 4
+# forcing schemes: Scheme II without G_i, Scheme II with G_i, Scheme I (Guo)
+FORCING_II, FORCING_II_G, FORCING_GUO = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -59,6 +61,15 @@ def _load():
         lib.ptrt_oracle_collide_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                                   _dp, ctypes.c_double, ctypes.c_double, _dp]
         lib.ptrt_oracle_fifth_modes.argtypes = [ctypes.c_int, _dp]
+        lib.ptrt_oracle_run_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
+                                           ctypes.c_int, ctypes.c_int]
+        lib.ptrt_oracle_phi_gradient.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, _dp, _u8p, _dp, _dp]
+        lib.ptrt_oracle_collide_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                               ctypes.c_double, _dp]
         lib.ptrt_oracle_max_threads.argtypes = []
         _lib = lib
     return _lib
@@ -144,6 +155,22 @@ def collide_model(lat, model, f, g, tau_plus, tau_minus):
     return out
 
 
+def collide_ex(lat, model, forcing, f, g, tau_plus, tau_minus, dphi=None):
+    """Collision of independent nodes with a model and a forcing scheme;
+    dphi [n,3] = d_a (rho u_a^3) per node (Scheme II with G_i)."""
+    f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, _Q[lat]))
+    out = np.zeros_like(f)
+    dp = None
+    if dphi is not None:
+        dp = np.ascontiguousarray(np.asarray(dphi, dtype=np.float64).reshape(f.shape[0], 3))
+    rc = _load().ptrt_oracle_collide_ex(lat, int(model), int(forcing), f.shape[0], _p(f),
+                                        _p(_g3(g)), _p(dp) if dp is not None else None,
+                                        tau_plus, tau_minus, _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle collide_ex failed ({rc})")
+    return out
+
+
 def fifth_modes(lat=D3Q27):
     """psi^(5,k) of D3Q27 as rows [3,27] (App. A.3)."""
     psi = np.zeros((3, 27))
@@ -169,9 +196,10 @@ class Lattice:
     """
 
     def __init__(self, lat, nx, ny, nz, tau_plus, Lambda, g=None, solid=None,
-                 tau_minus=None, nthreads=0, model=0):
+                 tau_minus=None, nthreads=0, model=0, forcing=0):
         self.lat = lat
         self.model = int(model)  # PTRT, TRT, PTRT_EXACT or PTRT_GHOST
+        self.forcing = int(forcing)  # FORCING_II, FORCING_II_G or FORCING_GUO
         self.Q = _Q[lat]
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
@@ -208,12 +236,21 @@ class Lattice:
     def step(self, n=1):
         nz, ny, nx = self.shape
         solid = _p(self.solid, _u8p) if self.solid is not None else None
-        rc = _load().ptrt_oracle_run_model(self.lat, self.model, nx, ny, nz, self.tau_plus,
-                                           self.Lambda, self.tau_minus, _p(self.g), solid,
-                                           _p(self.f), int(n), self.nthreads)
+        rc = _load().ptrt_oracle_run_ex(self.lat, self.model, self.forcing, nx, ny, nz,
+                                        self.tau_plus, self.Lambda, self.tau_minus, _p(self.g),
+                                        solid, _p(self.f), int(n), self.nthreads)
         if rc != 0:
             raise RuntimeError(f"oracle run failed ({rc})")
         self.t += n
+
+    def phi_gradient(self):
+        """d_a (rho u_a^3) of the current state at every node, [N,3]."""
+        nz, ny, nx = self.shape
+        out = np.zeros((self.N, 3))
+        solid = _p(self.solid, _u8p) if self.solid is not None else None
+        _load().ptrt_oracle_phi_gradient(self.lat, nx, ny, nz, _p(self.g), solid, _p(self.f),
+                                         _p(out))
+        return out
 
     def step_sampled(self, nodes):
         """f(t+1) at the given flat node indices, [len(nodes), Q]; state unchanged."""

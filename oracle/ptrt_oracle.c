@@ -21,8 +21,22 @@
  *     (1/2) w_i e_i.F / c_s^2, so the update is
  *       f* = f^eq + (1-1/tau+) R2 + (1-1/tau-) R3 + (1/2) w_i e_i.F / c_s^2
  *     with R3 from Eq. R3_force.  This keeps sum_i e_i f*_i = sum_i e_i f_i + F.
- *  R2 (cubic correction G_i of Eq. Gi) is omitted: it needs a spatial
- *     derivative of rho u^3 and vanishes for the channel flows.
+ *  R2 (cubic correction G_i of Eq. Gi).  The default update omits it; the
+ *     forcing FORCING_II_G adds it.  Phi_aaa = rho u_a^3 (u from Eq.
+ *     macro) for a = x, y and, in 3D, z (the printed list names x and y for
+ *     the 2D lattice); the derivative is the central difference
+ *     (Phi(x + e_a) - Phi(x - e_a)) / 2 with periodic wrap, and Phi = 0 at
+ *     solid nodes (the wall velocity is zero).
+ *  R17 (Scheme I, Eq. source_guo).  As printed, the -u.F/c_s^2 part sits
+ *     under the tau- factor, so sum_i S_i = (u.F/c_s^2)(1/(2 tau-) -
+ *     1/(2 tau+)) and mass is not conserved unless tau+ = tau-.  The
+ *     oracle moves that part under the tau+ factor (the usual TRT split:
+ *     symmetric part w_i (1 - 1/(2 tau+)) H2_i : uF / c_s^4, antisymmetric
+ *     part w_i (1 - 1/(2 tau-)) e_i.F / c_s^2), and with Scheme I the tau-
+ *     bracket holds f^{neq,-} alone: f* = f^eq + (1-1/tau+) R2 +
+ *     (1-1/tau-) f^{neq,-} + S^I.  This gives a momentum gain of exactly F;
+ *     the half-force correction inside the tau- bracket of Eq. PTRT belongs
+ *     to Scheme II (R1).
  *  R3 (D3Q19 ghost basis).  The three products (e_a^2-c_s^2)(e_b^2-c_s^2)
  *     of Appendix A.2 are neither orthogonal to one another nor to the
  *     stress modes under the weighted inner product.  The ghost subspace of
@@ -30,13 +44,13 @@
  *     Gram-Schmidt against the mass mode, the stress modes and each other
  *     (weighted inner product sum_i w_i a_i b_i).  On D2Q9 the single
  *     product is already orthogonal and is left unchanged.
- *  R4 (force) F = rho g with g a constant acceleration (Sec. 3.3).
+ *  R6 (force) F = rho g with g a constant acceleration (Sec. 3.3).
  *  Standard TRT (Eq. collision_TRT), used only as a comparison model, is
  *     the same update without the ghost subtraction.
- *  R5 (time step) collide, then stream (left side of Eq. PTRT); halfway
+ *  R7 (time step) collide, then stream (left side of Eq. PTRT); halfway
  *     bounce-back sends a population whose target node is solid back into
  *     the opposite direction of its source node (Sec. 3.3).
- *  R6 (D3Q27, App. A.3).  P-TRT on D3Q27 is the hybrid of Eq. PTRT_D3Q27:
+ *  R14 (D3Q27, App. A.3).  P-TRT on D3Q27 is the hybrid of Eq. PTRT_D3Q27:
  *     R2 is the Hermite stress projection w_i H2_i : A2 / (2 c_s^4) of
  *     f^neq, R3 is f^{neq,-} plus the force correction; the "exact" variant
  *     also subtracts the projections onto the three fifth-order modes
@@ -250,7 +264,7 @@ static int make_lattice(int id, Lattice *L)
 
 /* ------------------------------------------------------ per-node operators */
 
-/* Eq. macro with F = rho g (R4): rho = sum f, rho u = sum e f + F/2. */
+/* Eq. macro with F = rho g (R6): rho = sum f, rho u = sum e f + F/2. */
 static void moments(const Lattice *L, const double *f, const double g[3],
                     double *rho, double u[3])
 {
@@ -350,11 +364,44 @@ static void fifth_order_projection(const Lattice *L, const double *fneq, double 
     }
 }
 
-/* One collision f -> f*, Eq. PTRT with R1 (Eq. PTRT_D3Q27 on D3Q27, R6).
+/* One collision f -> f*, Eq. PTRT with R1 (Eq. PTRT_D3Q27 on D3Q27, R14).
  * MODEL_TRT skips the ghost subtraction, which is standard TRT (Eq.
  * collision_TRT: the ghost modes relax with tau+ like the stress modes). */
-static void collide_model(const Lattice *L, const double *f, const double g[3],
-                          double tau_p, double tau_m, int model, double *fstar)
+/* Forcing schemes (Sec. 2.1). */
+enum {
+    FORCING_II = 0,   /* Scheme II without G_i, net source of R1 */
+    FORCING_II_G = 1, /* Scheme II with the cubic correction G_i (Eq. Gi, R2) */
+    FORCING_GUO = 2   /* Scheme I, Eq. source_guo with the split of R17 */
+};
+
+/* Eq. Gi: G_i = -w_i H2_i,ab / (6 c_s^6) (1 - 1/(2 tau+)) d_c Phi_abc, with
+ * Phi_abc non-zero only for a = b = c; dphi[a] = d_a Phi_aaa. */
+static double cubic_correction(const Lattice *L, int i, double tau_p, const double dphi[3])
+{
+    double c = 0.0;
+    for (int a = 0; a < L->D; ++a) c += hermite2(L, i, a, a) * dphi[a];
+    double cs6 = L->cs2 * L->cs2 * L->cs2;
+    return -L->w[i] * c / (6.0 * cs6) * (1.0 - 1.0 / (2.0 * tau_p));
+}
+
+/* Eq. source_guo with the split of R17. */
+static double guo_source(const Lattice *L, int i, double tau_p, double tau_m, const double u[3],
+                         const double F[3])
+{
+    double eu = 0.0, eF = 0.0, uF = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        eu += L->e[i][a] * u[a];
+        eF += L->e[i][a] * F[a];
+        uF += u[a] * F[a];
+    }
+    double cs2 = L->cs2, cs4 = cs2 * cs2;
+    return L->w[i] * ((1.0 - 1.0 / (2.0 * tau_p)) * (eu * eF / cs4 - uF / cs2) +
+                      (1.0 - 1.0 / (2.0 * tau_m)) * eF / cs2);
+}
+
+static void collide_full(const Lattice *L, const double *f, const double g[3], double tau_p,
+                         double tau_m, int model, int forcing, const double dphi[3],
+                         double *fstar)
 {
     double rho, u[3], feq[QMAX], fneq[QMAX], plus[QMAX], minus[QMAX], pg[QMAX];
     double R2[QMAX], p5[QMAX];
@@ -378,10 +425,37 @@ static void collide_model(const Lattice *L, const double *f, const double g[3],
         for (int i = 0; i < L->Q; ++i) p5[i] = 0.0;
     double F[3] = {rho * g[0], rho * g[1], rho * g[2]};
     for (int i = 0; i < L->Q; ++i) {
+        if (forcing == FORCING_GUO) {
+            double R3 = minus[i] - p5[i];
+            fstar[i] = feq[i] + (1.0 - 1.0 / tau_p) * R2[i] + (1.0 - 1.0 / tau_m) * R3 +
+                       guo_source(L, i, tau_p, tau_m, u, F);
+            continue;
+        }
         double eF = L->e[i][0] * F[0] + L->e[i][1] * F[1] + L->e[i][2] * F[2];
         double half_force = 0.5 * L->w[i] * eF / L->cs2;
         double R3 = minus[i] - p5[i] + half_force; /* Eq. R3_force */
         fstar[i] = feq[i] + (1.0 - 1.0 / tau_p) * R2[i] + (1.0 - 1.0 / tau_m) * R3 + half_force;
+        if (forcing == FORCING_II_G) fstar[i] += cubic_correction(L, i, tau_p, dphi);
+    }
+}
+
+static void collide_model(const Lattice *L, const double *f, const double g[3],
+                          double tau_p, double tau_m, int model, double *fstar)
+{
+    collide_full(L, f, g, tau_p, tau_m, model, FORCING_II, NULL, fstar);
+}
+
+/* Phi_aaa = rho u_a^3 at every node (0 at solid nodes), [N][3] (R2). */
+static void phi_field(const Lattice *L, size_t N, const double *f, const double g[3],
+                      const uint8_t *solid, double *phi)
+{
+#pragma omp parallel for schedule(static)
+    for (long long m = 0; m < (long long)N; ++m) {
+        double rho, u[3];
+        for (int a = 0; a < 3; ++a) phi[3 * m + a] = 0.0;
+        if (solid && solid[m]) continue;
+        moments(L, f + m * L->Q, g, &rho, u);
+        for (int a = 0; a < L->D; ++a) phi[3 * m + a] = rho * u[a] * u[a] * u[a];
     }
 }
 
@@ -474,15 +548,33 @@ static size_t node_index(int x, int y, int z, int nx, int ny)
 
 static int wrap(int v, int n) { return ((v % n) + n) % n; }
 
+/* Central difference d_a Phi_aaa at node m with periodic wrap (R2). */
+static void phi_gradient(const Lattice *L, int nx, int ny, int nz, const double *phi, size_t m,
+                         double dphi[3])
+{
+    int x = (int)(m % nx), y = (int)((m / nx) % ny), z = (int)(m / ((size_t)nx * ny));
+    int c[3] = {x, y, z}, n[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        dphi[a] = 0.0;
+        if (a >= L->D) continue;
+        int p[3] = {x, y, z}, q[3] = {x, y, z};
+        p[a] = wrap(c[a] + 1, n[a]);
+        q[a] = wrap(c[a] - 1, n[a]);
+        dphi[a] = 0.5 * (phi[3 * node_index(p[0], p[1], p[2], nx, ny) + a] -
+                         phi[3 * node_index(q[0], q[1], q[2], nx, ny) + a]);
+    }
+}
+
 /*
  * Advance f [N][Q] (pre-collision populations at time t) by nsteps steps:
- * collide every fluid node (Eq. PTRT, R1), then stream with periodic wrap
- * and halfway bounce-back at solid neighbours (R5).  Populations stored at
- * solid nodes are not touched.  tau_minus <= 0 means "derive from Lambda".
+ * collide every fluid node (Eq. PTRT, R1; the forcing scheme as selected),
+ * then stream with periodic wrap and halfway bounce-back at solid
+ * neighbours (R7).  Populations stored at solid nodes are not touched.
+ * tau_minus <= 0 means "derive from Lambda".
  */
-int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_plus,
-                          double Lambda, double tau_minus, const double g[3],
-                          const uint8_t *solid, double *f, int nsteps, int nthreads)
+int ptrt_oracle_run_ex(int id, int model, int forcing, int nx, int ny, int nz, double tau_plus,
+                       double Lambda, double tau_minus, const double g[3], const uint8_t *solid,
+                       double *f, int nsteps, int nthreads)
 {
     Lattice L;
     if (make_lattice(id, &L)) return -1;
@@ -490,22 +582,31 @@ int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_
     if (model != MODEL_PTRT && model != MODEL_TRT && model != MODEL_PTRT_EXACT &&
         model != MODEL_PTRT_GHOST)
         return -4;
+    if (forcing != FORCING_II && forcing != FORCING_II_G && forcing != FORCING_GUO) return -5;
     double tau_m = tau_minus > 0.0 ? tau_minus : tau_minus_from_lambda(tau_plus, Lambda);
     int Q = L.Q;
     size_t N = (size_t)nx * ny * nz;
     double *fstar = (double *)malloc(N * Q * sizeof(double));
-    if (!fstar) return -3;
+    double *phi = forcing == FORCING_II_G ? (double *)malloc(N * 3 * sizeof(double)) : NULL;
+    if (!fstar || (forcing == FORCING_II_G && !phi)) {
+        free(fstar);
+        free(phi);
+        return -3;
+    }
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
     (void)nthreads;
 #endif
     for (int step = 0; step < nsteps; ++step) {
+        if (phi) phi_field(&L, N, f, g, solid, phi);
         /* collision */
 #pragma omp parallel for schedule(static)
         for (long long m = 0; m < (long long)N; ++m) {
             if (solid && solid[m]) continue;
-            collide_model(&L, f + m * Q, g, tau_plus, tau_m, model, fstar + m * Q);
+            double dphi[3] = {0.0, 0.0, 0.0};
+            if (phi) phi_gradient(&L, nx, ny, nz, phi, (size_t)m, dphi);
+            collide_full(&L, f + m * Q, g, tau_plus, tau_m, model, forcing, dphi, fstar + m * Q);
         }
         /* streaming, left side of Eq. PTRT, with halfway bounce-back */
 #pragma omp parallel for schedule(static)
@@ -524,6 +625,51 @@ int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_
         }
     }
     free(fstar);
+    free(phi);
+    return 0;
+}
+
+int ptrt_oracle_run_model(int id, int model, int nx, int ny, int nz, double tau_plus,
+                          double Lambda, double tau_minus, const double g[3],
+                          const uint8_t *solid, double *f, int nsteps, int nthreads)
+{
+    return ptrt_oracle_run_ex(id, model, FORCING_II, nx, ny, nz, tau_plus, Lambda, tau_minus, g,
+                              solid, f, nsteps, nthreads);
+}
+
+/* d_a Phi_aaa at every node of the state f [N][Q] -> dphi [N][3] (R2). */
+int ptrt_oracle_phi_gradient(int id, int nx, int ny, int nz, const double g[3],
+                             const uint8_t *solid, const double *f, double *dphi)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    size_t N = (size_t)nx * ny * nz;
+    double *phi = (double *)malloc(N * 3 * sizeof(double));
+    if (!phi) return -3;
+    phi_field(&L, N, f, g, solid, phi);
+    for (size_t m = 0; m < N; ++m) phi_gradient(&L, nx, ny, nz, phi, m, dphi + 3 * m);
+    free(phi);
+    return 0;
+}
+
+/* Collision of n independent nodes with a model and a forcing scheme; dphi
+ * [n][3] holds d_a Phi_aaa per node (used by FORCING_II_G, may be NULL
+ * otherwise). */
+int ptrt_oracle_collide_ex(int id, int model, int forcing, int n, const double *f_in,
+                           const double g[3], const double *dphi, double tau_plus,
+                           double tau_minus, double *f_out)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    if (model != MODEL_PTRT && model != MODEL_TRT && model != MODEL_PTRT_EXACT &&
+        model != MODEL_PTRT_GHOST)
+        return -4;
+    if (forcing != FORCING_II && forcing != FORCING_II_G && forcing != FORCING_GUO) return -5;
+    if (forcing == FORCING_II_G && !dphi) return -5;
+    static const double zero[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < n; ++m)
+        collide_full(&L, f_in + (size_t)m * L.Q, g, tau_plus, tau_minus, model, forcing,
+                     dphi ? dphi + 3 * (size_t)m : zero, f_out + (size_t)m * L.Q);
     return 0;
 }
 
@@ -578,7 +724,7 @@ int ptrt_oracle_fifth_modes(int id, double *psi_out)
  * One step evaluated only at the listed nodes: out[s][i] = f_i(x_s, t+1)
  * for the pre-collision state f at time t.  Each sampled population is
  * obtained from the collision at its source node x_s - e_i, or at x_s itself
- * with the opposite direction when that source is solid (R5).  Used to check
+ * with the opposite direction when that source is solid (R7).  Used to check
  * lattices too large for a whole-lattice oracle run.
  */
 int ptrt_oracle_step_sampled(int id, int nx, int ny, int nz, double tau_plus,

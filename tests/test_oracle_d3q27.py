@@ -4,7 +4,7 @@
   conditions up to sixth order (exact rationals).
 * Modes: the seven printed ghost modes and the three fifth-order modes in
   exact rationals: mutually orthogonal, orthogonal to the hydrodynamic and
-  third-order modes; the oracle's basis equals the printed one.  Reading R6:
+  third-order modes; the oracle's basis equals the printed one.  Reading R14:
   psi^(5,x) is not zero off the body diagonals.
 * Collision: the hybrid R2 (tensor projection) equals the ghost subtraction
   of Eq. PTRT (Theorem 2); the exact variant equals TRT-RLB (NumPy);
@@ -113,10 +113,10 @@ def test_printed_ghost_modes_are_orthogonal_and_oracle_keeps_them():
         assert abs(nrm[k] - float(_dot(w, gh[k], gh[k]))) < 1e-16
 
 
-def test_fifth_order_modes_and_reading_r6():
+def test_fifth_order_modes_and_reading_r14():
     """The three fifth-order modes span the antisymmetric deficit: orthogonal
     to H1, the seven third-order modes and each other, norm 4/243.  They are
-    not zero off the body diagonals (reading R6): psi^(5,x) = 1/9 at
+    not zero off the body diagonals (reading R14): psi^(5,x) = 1/9 at
     (1,0,0) and -2/9 at (1,1,0)."""
     ev, w = _exact_lattice()
     psi = _printed_fifth(ev)
