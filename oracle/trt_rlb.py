@@ -12,7 +12,13 @@ Readings (the same as the C oracle's where they overlap):
 * tau_{s,1} also relaxes the first-order non-equilibrium moment (the sentence
   after Eq. TRT-RLB; order-epsilon Chapman-Enskog equation).  That term is
   computed here from f^neq itself: w_i e_ia (sum_j e_ja f^neq_j) / c_s^2.
-* Source term: Scheme II without the cubic correction G_i (Eq. source_simple).
+* Source term: Scheme II (Eq. source_simple), with or without the cubic
+  correction G_i (Eq. Gi; Phi_aaa = rho u_a^3, central differences with
+  periodic wrap, Phi = 0 at solid nodes), or Scheme I (Eq. source_guo) with
+  the -u.F/c_s^2 part under the tau+ factor (as printed it sits under the
+  tau- factor, which does not conserve mass).  With Scheme I the first-order
+  non-equilibrium moment relaxes with tau- (standard TRT, the antisymmetric
+  rate), which gives a momentum gain of exactly F.
 * Third-order reconstruction on D3Q19.  The literal tensor contraction of
   Eq. R2R3_hermite is an orthogonal projection only if the independent
   third-order Hermite polynomials are mutually orthogonal under the weighted
@@ -132,12 +138,14 @@ def reconstruct_third_projection(e, w, fneq):
     return w[None] * (A @ np.linalg.inv(G) @ M)
 
 
-def collide(lattice_name, f, g, tau_plus, tau_minus, third="auto"):
+def collide(lattice_name, f, g, tau_plus, tau_minus, third="auto", scheme="II", dphi=None):
     """TRT-RLB post-collision state, f [n,Q] -> [n,Q] (Eq. TRT-RLB).
 
     g is the body acceleration (F = rho g).  ``third`` selects the third-order
     reconstruction: "literal", "projection" or "auto" (literal on D2Q9 and
-    D3Q27, projection on D3Q19)."""
+    D3Q27, projection on D3Q19).  ``scheme``: "II" (Eq. source_simple without
+    G_i), "II+G" (with G_i; ``dphi`` [n,D] holds d_a Phi_aaa per node) or
+    "I" (Eq. source_guo, mass-conserving split)."""
     e, w = lattice(lattice_name)
     D = e.shape[1]
     g = np.zeros(D) if g is None else np.asarray(g, dtype=np.float64)[:D]
@@ -154,8 +162,42 @@ def collide(lattice_name, f, g, tau_plus, tau_minus, third="auto"):
         third = "projection" if lattice_name == "D3Q19" else "literal"
     R3 = (reconstruct_third_literal if third == "literal" else reconstruct_third_projection)(e, w, fneq)
     P1 = w[None] * ((fneq @ e) @ e.T) / CS2                  # first-order part
-    S = (1 - 1 / (2 * tau_plus)) * w[None] * (F @ e.T) / CS2  # Scheme II, G_i = 0
-    return feq + (1 - 1 / tau_plus) * (R2 + P1) + (1 - 1 / tau_minus) * R3 + S
+    ap, am = 1 - 1 / tau_plus, 1 - 1 / tau_minus
+    bp, bm = 1 - 1 / (2 * tau_plus), 1 - 1 / (2 * tau_minus)
+    if scheme == "I":
+        eu, eF = u @ e.T, F @ e.T
+        uF = (u * F).sum(1)[:, None]
+        S = w[None] * (bp * (eu * eF / CS2 ** 2 - uF / CS2) + bm * eF / CS2)
+        return feq + ap * R2 + am * (P1 + R3) + S
+    S = bp * w[None] * (F @ e.T) / CS2                       # Scheme II
+    if scheme == "II+G":
+        T = np.einsum("na,ab->nab", np.asarray(dphi, dtype=np.float64)[:, :D], np.eye(D))
+        S = S - bp * w[None] * np.einsum("iab,nab->ni", H2, T) / (6 * CS2 ** 3)
+    elif scheme != "II":
+        raise ValueError(scheme)
+    return feq + ap * (R2 + P1) + am * R3 + S
+
+
+def phi_gradient(lattice_name, f, shape, g, solid=None):
+    """d_a (rho u_a^3) by central differences with periodic wrap, Phi = 0 at
+    solid nodes; f [Q, *shape] -> [N, D]."""
+    e, _ = lattice(lattice_name)
+    Q, D = e.shape
+    fl = f.reshape(Q, -1)
+    rho = fl.sum(0)
+    g = np.zeros(D) if g is None else np.asarray(g, dtype=np.float64)[:D]
+    safe = np.where(rho == 0.0, 1.0, rho)                      # solid nodes hold zeros
+    u = (e.T @ fl + 0.5 * rho[None] * g[:, None]) / safe[None]
+    phi = rho[None] * u ** 3
+    if solid is not None:
+        phi[:, np.asarray(solid, dtype=bool).ravel()] = 0.0
+    nd = len(shape)
+    out = np.zeros((fl.shape[1], D))
+    for a in range(D):
+        axis = nd - 1 - a                                     # x is the last array axis
+        p = phi[a].reshape(shape)
+        out[:, a] = (0.5 * (np.roll(p, -1, axis=axis) - np.roll(p, 1, axis=axis))).ravel()
+    return out
 
 
 def stream(lattice_name, fstar, shape, solid=None):
@@ -184,7 +226,7 @@ def stream(lattice_name, fstar, shape, solid=None):
     return out
 
 
-def run(lattice_name, f, shape, g, tau_plus, tau_minus, nsteps, solid=None):
+def run(lattice_name, f, shape, g, tau_plus, tau_minus, nsteps, solid=None, scheme="II"):
     """Advance populations f [Q, *shape] by nsteps TRT-RLB steps."""
     e, _ = lattice(lattice_name)
     Q = e.shape[0]
@@ -192,11 +234,13 @@ def run(lattice_name, f, shape, g, tau_plus, tau_minus, nsteps, solid=None):
     sol = None if solid is None else np.asarray(solid, dtype=bool).reshape(shape)
     for _ in range(nsteps):
         flat = f.reshape(Q, -1).T
+        dphi = phi_gradient(lattice_name, f, shape, g, sol) if scheme == "II+G" else None
         if sol is None:
-            fs = collide(lattice_name, flat, g, tau_plus, tau_minus)
+            fs = collide(lattice_name, flat, g, tau_plus, tau_minus, scheme=scheme, dphi=dphi)
         else:
             fs = np.zeros_like(flat)
             fl = ~sol.ravel()
-            fs[fl] = collide(lattice_name, flat[fl], g, tau_plus, tau_minus)
+            fs[fl] = collide(lattice_name, flat[fl], g, tau_plus, tau_minus, scheme=scheme,
+                             dphi=None if dphi is None else dphi[fl])
         f = stream(lattice_name, fs.T.reshape(f.shape), shape, sol)
     return f
