@@ -8,8 +8,9 @@ D3Q19 512^3 with FP32 vs FP16 vs BF16 shifted storage, the batched D2Q9
 form (512 uneven lattices, one graph-replayed launch per step, and the
 one-launch-per-lattice comparison), and the two D2Q9 single-lattice
 configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64),
-the collision-model comparison, and D3Q27 (hybrid P-TRT, FP32 / FP16, and
-its comparison models) on the 256^3 vortex.
+the collision-model comparison, D3Q27 (hybrid P-TRT, FP32 / FP16, and
+its comparison models) on the 256^3 vortex, and the forcing schemes
+(Scheme II with the cubic correction, Scheme I) against the default.
 
 ``roofline`` describes the dominant kernel (the D3Q19 FP32 step): the
 algorithmic bytes per launch (2 * 19 * 4 bytes per node) over the average
@@ -35,7 +36,8 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d3q19_f32_256_traffic.json")
 KERNEL_SOURCES = ["paper_2602_06686_amd/csrc/kernels.hpp", "paper_2602_06686_amd/csrc/collide.hpp",
                   "paper_2602_06686_amd/csrc/codec.hpp", "paper_2602_06686_amd/csrc/lattice.hpp",
-                  "paper_2602_06686_amd/csrc/trt_rlb.hpp", "paper_2602_06686_amd/csrc/ptrt_single.hip"]
+                  "paper_2602_06686_amd/csrc/trt_rlb.hpp", "paper_2602_06686_amd/csrc/step_launch.hpp",
+                  "paper_2602_06686_amd/csrc/step_d3q19.hip", "paper_2602_06686_amd/csrc/ptrt_single.hip"]
 
 
 def log(*a):
@@ -219,6 +221,40 @@ def form_d3q27(P, torch, stream, steps, warmup):
     return out
 
 
+def form_forcing(P, torch, stream, steps, warmup):
+    """Forcing schemes (Sec. 2.1) in the same harness, FP32: Scheme II
+    (default), Scheme II with the cubic correction G_i (a Phi pass of Q reads
+    and D writes per node before the fused step, which also reads Phi at the
+    2D axis neighbours) and Scheme I (Guo), on the 256^3 D3Q19 vortex and
+    the 2048^2 D2Q9 shear layer, each with a uniform acceleration of 1e-6."""
+    import lbm_inputs as I
+    out = {}
+    n3, n2, U0 = 256, 2048, 0.05
+    cases = ((P.PTRT_D3Q19, (n3, n3, n3), I.tgv3d_params(n3)["tau_plus"],
+              lambda: I.tgv3d(n3, U0), 19, 3, "d3q19_256_tgv"),
+             (P.PTRT_D2Q9, (1, n2, n2), I.tau_plus_from_nu(U0 * n2 / 1e4),
+              lambda: I.double_shear_layer(n2, U0), 9, 2, "d2q9_2048_dsl"))
+    for lat, shape, tp, init, Q, D, key in cases:
+        nz, ny, nx = shape
+        nodes = nx * ny * nz
+        rho, u = init()
+        res = {}
+        for forcing in ("scheme2", "scheme2+g", "guo"):
+            with P.Lattice(lat, nx, ny, nz, tp, 0.25, force=[1e-6, 0, 0], storage="f32",
+                           stream=stream, forcing=forcing) as L:
+                L.init_equilibrium(rho, u)
+                ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+            mps = ms / steps
+            alg = 2 * Q * 4 + (Q * 4 + 2 * D * 4 if forcing == "scheme2+g" else 0)
+            res[forcing] = {"ms_per_step": mps, "mlups": nodes / (mps * 1e-3) / 1e6,
+                            "algorithmic_bytes_per_node": alg,
+                            "achieved_gbs": alg * nodes / (mps * 1e-3) / 1e9}
+        res["g_time_over_scheme2"] = res["scheme2+g"]["ms_per_step"] / res["scheme2"]["ms_per_step"]
+        res["guo_time_over_scheme2"] = res["guo"]["ms_per_step"] / res["scheme2"]["ms_per_step"]
+        out[key] = res
+    return out
+
+
 def cpu_baseline(n=256, steps=12):
     """The FP64 C oracle, as it is, on `steps` steps of the headline lattice."""
     import lbm_inputs as I
@@ -266,7 +302,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default=None,
                     help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, models, "
-                         "d3q27, tgv64")
+                         "d3q27, forcing, tgv64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -316,6 +352,10 @@ def main():
         log("D3Q27 256^3")
         forms["d3q27_256"] = form_d3q27(P, torch, stream, max(20, K // 2), max(2, W // 2))
         log(json.dumps(forms["d3q27_256"]))
+    if only in (None, "forcing"):
+        log("forcing schemes")
+        forms["forcing_fp32"] = form_forcing(P, torch, stream, max(20, K // 2), max(2, W // 2))
+        log(json.dumps(forms["forcing_fp32"]))
     if only in (None, "tgv64"):
         log("D2Q9 FP64 64^2")
         forms["d2q9_64_f64"] = form_tgv64(P, torch, stream, 1000, 50)

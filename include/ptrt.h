@@ -90,6 +90,28 @@ enum ptrt_storage { PTRT_F64 = 0, PTRT_F32 = 1, PTRT_F16 = 2, PTRT_BF16 = 3 };
  * fifth-order antisymmetric modes; PTRT_MODEL_PTRT_EXACT projects those out
  * as well (App. A.3), which equals TRT-RLB.  On D2Q9 and D3Q19
  * PTRT_MODEL_PTRT_EXACT is the same as PTRT_MODEL_PTRT. */
+/* Forcing schemes (Sec. 2.1), all with F = rho * force and the half-force
+ * velocity of Eq. macro:
+ *   PTRT_FORCING_SCHEME2    Scheme II (Eq. source_simple) without the cubic
+ *                           correction; the first-order non-equilibrium
+ *                           moment relaxes with tau+, which leaves the net
+ *                           source (1/2) w_i e_i.F / c_s^2 in Eq. PTRT and a
+ *                           momentum gain of exactly F per step (default);
+ *   PTRT_FORCING_SCHEME2_G  the same plus G_i of Eq. Gi, with
+ *                           Phi_aaa = rho u_a^3 (a = x, y and, in 3D, z),
+ *                           d_a Phi_aaa by central differences with
+ *                           periodic wrap, Phi = 0 at solid nodes; each step
+ *                           runs a Phi pass before the fused step;
+ *   PTRT_FORCING_GUO        Scheme I (Eq. source_guo) with its -u.F/c_s^2
+ *                           part under the tau+ factor (as printed it sits
+ *                           under the tau- factor and does not conserve
+ *                           mass); the tau- bracket then holds f^neq,- alone. */
+enum ptrt_forcing {
+    PTRT_FORCING_SCHEME2 = 0,
+    PTRT_FORCING_SCHEME2_G = 1,
+    PTRT_FORCING_GUO = 2
+};
+
 enum ptrt_model {
     PTRT_MODEL_PTRT = 0,
     PTRT_MODEL_TRT_RLB = 1,
@@ -127,8 +149,18 @@ int ptrt_set_storage(ptrt_ctx *ctx, int storage);
 
 /* Select the collision model (enum ptrt_model) for later steps; allowed at
  * any time (waits for the handle's stream).  The comparison models need
- * ny <= 65535 and nz <= 65535.  Default PTRT_MODEL_PTRT. */
+ * ny <= 65535 and nz <= 65535, and run with PTRT_FORCING_SCHEME2 only
+ * (PTRT_EINVAL otherwise).  Default PTRT_MODEL_PTRT. */
 int ptrt_set_model(ptrt_ctx *ctx, int model);
+
+/* Select the forcing scheme (enum ptrt_forcing) for later steps; allowed at
+ * any time (waits for the handle's stream).  The variants other than
+ * PTRT_FORCING_SCHEME2 need model PTRT_MODEL_PTRT or PTRT_MODEL_PTRT_EXACT
+ * and ny, nz <= 65535 (PTRT_EINVAL otherwise).  PTRT_FORCING_SCHEME2_G
+ * allocates the Phi field (D values per node in the compute type: FP64 for
+ * FP64 storage, FP32 otherwise), owned by the handle; PTRT_ENOMEM if that
+ * fails.  Default PTRT_FORCING_SCHEME2. */
+int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
 
 /* Stream for all later work of this handle; a hipStream_t passed as void*
  * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */

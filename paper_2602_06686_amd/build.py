@@ -6,6 +6,7 @@ calls :func:`build`.  hipcc cross-compiles, so no GPU is needed.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -13,14 +14,15 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libptrt.so")
 
-SOURCES = ["ptrt_single.hip", "ptrt_batch.hip"]
+SOURCES = ["ptrt_single.hip", "step_d2q9.hip", "step_d3q19.hip", "step_d3q27.hip",
+           "ptrt_batch.hip"]
+BUILD_DIR = os.path.join(PKG, "_build")
 
-HIPCC_FLAGS = [
+COMPILE_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # FMA contraction only inside one expression: the same source expression
     # gives the same rounding in every kernel it is inlined into
     "-ffp-contract=on",
@@ -35,15 +37,32 @@ def hipcc():
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", LIB + ".tmp"] + srcs
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(BUILD_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+    cmd = [hipcc()] + COMPILE_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libptrt.so")
+        raise RuntimeError(f"hipcc failed compiling {os.path.basename(src)}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every translation unit (in parallel) and link libptrt.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libptrt.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -60,7 +60,49 @@ struct Coef {
     C hgx, hgy, hgz;    // g / 2
     C K[L::NP];         // (1 + a-) (3/2) w_i e_i.g of the first member of each pair
     C K2[L::NP];        // 3 (1 - 1/(2 tau+)) w_i e_i.g (Scheme II source, TRT-RLB form)
+    C bp6;              // 6 (1 - 1/(2 tau+)): Scheme I, 3 b+ u.g = bp6 (u . g/2)
+    C G9[L::NP];        // 9 (1 - 1/(2 tau+)) w_i e_i.g: Scheme I, first member of each pair
+    C gphi;             // -(9/4) (1 - 1/(2 tau+)): G_i per unit Phi difference across 2 nodes
 };
+
+// Forcing schemes (Sec. 2.1).  FORCE_II: Scheme II without G_i, net source
+// (1/2) w_i e_i.F / c_s^2 (the default).  FORCE_II_G: plus the cubic
+// correction of Eq. Gi, G_i = -(9/2)(1 - 1/(2 tau+)) w_i sum_a (e_ia^2 - 1/3)
+// d_a(rho u_a^3), the derivative a central difference of a Phi field written
+// by a separate pass.  FORCE_GUO: Scheme I (Eq. source_guo) with its -u.F
+// part moved under the tau+ factor (the printed split does not conserve
+// mass); its antisymmetric part equals the default's, so it adds the
+// symmetric source (1 - 1/(2 tau+)) w_i rho (9 (e_i.u)(e_i.g) - 3 u.g).
+enum { FORCE_II = 0, FORCE_II_G = 1, FORCE_GUO = 2 };
+
+// Per-node symmetric source of the forcing schemes: dX are the scaled Phi
+// differences gphi (Phi(x + e_X) - Phi(x - e_X)) (FORCE_II_G), ug3 =
+// 3 (1 - 1/(2 tau+)) u.g (FORCE_GUO).
+template <class C>
+struct Src {
+    C dx, dy, dz, ug3;
+};
+
+template <class L, int FORCING, int I, class C>
+__device__ __forceinline__ C sym_source(const Src<C> &s, const Coef<L, C> &r, int p, C rho, C eu)
+{
+    constexpr double third = 1.0 / 3.0;
+    constexpr double w = L::w(I);
+    if constexpr (FORCING == FORCE_II_G) {
+        constexpr double cx = L::ex(I) * L::ex(I) - third, cy = L::ey(I) * L::ey(I) - third,
+                         cz = L::ez(I) * L::ez(I) - third;
+        C t = C(w * cx) * s.dx + C(w * cy) * s.dy;
+        if constexpr (L::D == 3) t += C(w * cz) * s.dz;
+        return t;
+    } else if constexpr (FORCING == FORCE_GUO) {
+        if constexpr (I == 0)
+            return -(C(w) * rho) * s.ug3;
+        else
+            return rho * (r.G9[p] * eu - C(w) * s.ug3);
+    } else {
+        return C(0);
+    }
+}
 
 template <class L, class C>
 inline Coef<L, C> make_coef(double tau_plus, double Lambda, const double g[3])
@@ -78,7 +120,10 @@ inline Coef<L, C> make_coef(double tau_plus, double Lambda, const double g[3])
         const double eg = L::ex(i) * g[0] + L::ey(i) * g[1] + L::ez(i) * g[2];
         c.K[p] = (C)((1.0 + am) * 1.5 * L::w(i) * eg);
         c.K2[p] = (C)(3.0 * (1.0 - 0.5 / tau_plus) * L::w(i) * eg);
+        c.G9[p] = (C)(9.0 * (1.0 - 0.5 / tau_plus) * L::w(i) * eg);
     }
+    c.bp6 = (C)(6.0 * (1.0 - 0.5 / tau_plus));
+    c.gphi = (C)(-2.25 * (1.0 - 0.5 / tau_plus));
     return c;
 }
 
@@ -161,9 +206,9 @@ __device__ __forceinline__ void shifted_moments(const C (&h)[L::Q], C &drho, C &
 // references (used by the fused diagnostics).
 // GHOST = false gives standard TRT (Eq. collision_TRT: the ghost modes
 // relax with tau+ like the stress modes); same force treatment.
-template <class L, class C, bool GHOST = true>
+template <class L, class C, bool GHOST = true, int FORCING = FORCE_II>
 __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rho_o, C &ux_o,
-                                        C &uy_o, C &uz_o)
+                                        C &uy_o, C &uz_o, Src<C> src = Src<C>{})
 {
     C sp[L::NP], dp[L::NP];
     static_for<L::NP>([&](auto pc) {
@@ -199,8 +244,11 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
         for (int p = 0; p < L::NP; ++p) pg[p] = C(0);
     }
 
+    if constexpr (FORCING == FORCE_GUO)
+        src.ug3 = r.bp6 * (ux * r.hgx + uy * r.hgy + uz * r.hgz);
     const C eq0 = C(L::w(0)) * (drho + rho * m15uu);
     h[0] = eq0 + r.ap * ((h[0] - eq0) - pg0);
+    if constexpr (FORCING != FORCE_II) h[0] += sym_source<L, FORCING, 0>(src, r, 0, rho, C(0));
     static_for<L::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int i = L::pair_first(p), j = L::opp(i);
@@ -208,7 +256,8 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
         const C eu = edot<L, i>(ux, uy, uz);
         const C eu2 = eu * eu;
         const C eqp = w * (drho + rho * (C(4.5) * eu2 + m15uu));
-        const C sym = eqp + r.ap * ((C(0.5) * sp[p] - eqp) - pg[p]);
+        C sym = eqp + r.ap * ((C(0.5) * sp[p] - eqp) - pg[p]);
+        if constexpr (FORCING != FORCE_II) sym += sym_source<L, FORCING, i>(src, r, p, rho, eu);
         const C eqm = (w * rho) * (eu * (C(3) + C(4.5) * (eu2 - uu)));
         const C anti = eqm + r.am * (C(0.5) * dp[p] - eqm) + rho * r.K[p];
         h[i] = sym + anti;
@@ -227,9 +276,9 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
 // antisymmetric modes psi_a = e_a (e_b^2 - c_s^2)(e_c^2 - c_s^2) are
 // projected out of f^neq,- first (weighted norm 4/243 each), which makes the
 // update equal to TRT-RLB on this lattice.
-template <class C, bool EXACT>
+template <class C, bool EXACT, int FORCING = FORCE_II>
 __device__ __forceinline__ void collide_d3q27(C (&h)[27], const Coef<D3Q27, C> &r, C &rho_o,
-                                              C &ux_o, C &uy_o, C &uz_o)
+                                              C &ux_o, C &uy_o, C &uz_o, Src<C> src = Src<C>{})
 {
     using L = D3Q27;
     C sp[L::NP], dp[L::NP];
@@ -313,7 +362,10 @@ __device__ __forceinline__ void collide_d3q27(C (&h)[27], const Coef<D3Q27, C> &
         S5z *= inv_norm;
     }
 
+    if constexpr (FORCING == FORCE_GUO)
+        src.ug3 = r.bp6 * (ux * r.hgx + uy * r.hgy + uz * r.hgz);
     h[0] = eq0 + r.ap * (C(L::w(0) * 4.5 * -third) * (Axx + Ayy + Azz));
+    if constexpr (FORCING != FORCE_II) h[0] += sym_source<L, FORCING, 0>(src, r, 0, rho, C(0));
     static_for<L::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int i = L::pair_first(p), j = L::opp(i);
@@ -336,7 +388,9 @@ __device__ __forceinline__ void collide_d3q27(C (&h)[27], const Coef<D3Q27, C> &
             if constexpr (pz != 0) p5 += C(w * pz) * S5z;
             R3 = R3 - p5;
         }
-        const C sym = eqp[p] + r.ap * R2;
+        C sym = eqp[p] + r.ap * R2;
+        if constexpr (FORCING != FORCE_II)
+            sym += sym_source<L, FORCING, i>(src, r, p, rho, edot<L, i>(ux, uy, uz));
         const C anti = eqm[p] + r.am * R3 + rho * r.K[p];
         h[i] = sym + anti;
         h[j] = sym - anti;

@@ -19,6 +19,23 @@ struct Tag {
     using type = T;
 };
 
+// Call f(Tag<S>, bool_constant<MASK>) for the runtime storage and mask.
+template <class F>
+inline int dispatch_storage(int storage, bool mask, F &&f)
+{
+    auto with_mask = [&](auto st) -> int {
+        if (mask) return f(st, std::true_type{});
+        return f(st, std::false_type{});
+    };
+    switch (storage) {
+    case PTRT_F64: return with_mask(Tag<double>{});
+    case PTRT_F32: return with_mask(Tag<float>{});
+    case PTRT_F16: return with_mask(Tag<_Float16>{});
+    case PTRT_BF16: return with_mask(Tag<bf16_t>{});
+    default: return PTRT_EINVAL;
+    }
+}
+
 // Call f(Tag<L>, Tag<S>, bool_constant<MASK>) for the runtime choice.
 template <class F>
 inline int dispatch(int lattice, int storage, bool mask, F &&f)

@@ -169,32 +169,119 @@ __device__ __forceinline__ unsigned flat_block()
 enum { MODEL_PTRT = 0, MODEL_TRT_RLB = 1, MODEL_TRT = 2, MODEL_PTRT_EXACT = 3 };
 
 // ---------------------------------------------------------------------------
+// Phi field of the cubic correction (Eq. Gi): Phi_a = rho u_a^3 of every
+// node at the current time, component-major [D][nz][ny][nx] in the compute
+// type, 0 at solid nodes.
+template <class C>
+__device__ __forceinline__ size_t phi_index(const Geom &g, int a, unsigned row, int x)
+{
+    return (size_t)a * ((size_t)g.ny * (size_t)g.nz * (size_t)g.nx) + (size_t)row * (unsigned)g.nx +
+           (unsigned)x;
+}
+
+// Scaled central differences of Phi at (x, y, z) with periodic wrap.
+template <class L, class C>
+__device__ __forceinline__ Src<C> phi_differences(const C *__restrict__ phi, const Geom &g,
+                                                  const Coef<L, C> &r, int x, int y, int z,
+                                                  unsigned row)
+{
+    const Nbr n(g, x, y, z);
+    Src<C> s{};
+    s.dx = r.gphi * (phi[phi_index<C>(g, 0, row, n.xp)] - phi[phi_index<C>(g, 0, row, n.xm)]);
+    const unsigned rym = (unsigned)z * (unsigned)g.ny + (unsigned)n.ym;
+    const unsigned ryp = (unsigned)z * (unsigned)g.ny + (unsigned)n.yp;
+    s.dy = r.gphi * (phi[phi_index<C>(g, 1, ryp, x)] - phi[phi_index<C>(g, 1, rym, x)]);
+    if constexpr (L::D == 3) {
+        const unsigned rzm = (unsigned)n.zm * (unsigned)g.ny + (unsigned)y;
+        const unsigned rzp = (unsigned)n.zp * (unsigned)g.ny + (unsigned)y;
+        s.dz = r.gphi * (phi[phi_index<C>(g, 2, rzp, x)] - phi[phi_index<C>(g, 2, rzm, x)]);
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
 // One node update: pull, moments, equilibrium, parity split, ghost removal,
 // two-rate relaxation, force; store to the node's own slots of dst.
-template <class L, class S, bool MASK, bool NT, int MODEL = MODEL_PTRT>
+template <class L, class S, bool MASK, bool NT, int MODEL = MODEL_PTRT, int FORCING = FORCE_II>
 __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__restrict__ dst,
                                             const uint8_t *__restrict__ mask, const Geom &g,
                                             const Coef<L, typename Codec<S>::compute> &r, int x,
-                                            int y, int z, unsigned row, double &m, double &k)
+                                            int y, int z, unsigned row, double &m, double &k,
+                                            const typename Codec<S>::compute *__restrict__ phi =
+                                                nullptr)
 {
     using C = typename Codec<S>::compute;
+    static_assert(MODEL != MODEL_TRT_RLB || FORCING == FORCE_II,
+                  "the TRT-RLB comparison kernel uses Scheme II only");
     C h[L::Q];
     pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
+    Src<C> sc{};
+    if constexpr (FORCING == FORCE_II_G) sc = phi_differences<L, C>(phi, g, r, x, y, z, row);
     C rho, ux, uy, uz;
     if constexpr (MODEL == MODEL_TRT_RLB)
         collide_trt_rlb<L, C>(h, r, rho, ux, uy, uz);
     else if constexpr (MODEL == MODEL_TRT)
-        collide<L, C, false>(h, r, rho, ux, uy, uz);
+        collide<L, C, false, FORCING>(h, r, rho, ux, uy, uz, sc);
     else if constexpr (L::Q == 27)
-        collide_d3q27<C, MODEL == MODEL_PTRT_EXACT>(h, r, rho, ux, uy, uz);
+        collide_d3q27<C, MODEL == MODEL_PTRT_EXACT, FORCING>(h, r, rho, ux, uy, uz, sc);
     else
-        collide<L, C, true>(h, r, rho, ux, uy, uz);
+        collide<L, C, true, FORCING>(h, r, rho, ux, uy, uz, sc);
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);
     });
     m = (double)rho;
     k = 0.5 * (double)rho * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
+}
+
+// Phi pass of the cubic correction: pull, moments (Eq. macro), Phi_a =
+// rho u_a^3; solid nodes write 0.  Same workgroup shapes as k_step.
+template <class L, class S, bool MASK, bool ROW>
+__global__ void __launch_bounds__(1024)
+k_phi(const S *__restrict__ src, const uint8_t *__restrict__ mask, const uint8_t *__restrict__ near,
+      Geom g, Coef<L, typename Codec<S>::compute> r, typename Codec<S>::compute *__restrict__ phi)
+{
+    using C = typename Codec<S>::compute;
+    int x, y, z;
+    if constexpr (ROW) {
+        x = blockIdx.x * blockDim.x + threadIdx.x;
+        y = blockIdx.y;
+        z = blockIdx.z;
+    } else {
+        x = blockIdx.x * blockDim.x + threadIdx.x;
+        y = blockIdx.y * blockDim.y + threadIdx.y;
+        z = blockIdx.z;
+    }
+    if (x >= g.nx || (!ROW && y >= g.ny)) return;
+    const unsigned row = (unsigned)z * (unsigned)g.ny + (unsigned)y;
+    C h[L::Q];
+    bool solid = false;
+    auto ld = [](const S *p) { return Codec<S>::load(p); };
+    if constexpr (MASK) {
+        solid = mask[row * (unsigned)g.nx + (unsigned)x] != 0;
+        if (!solid) {
+            if (near[row])
+                pull<L, S, true>(src, mask, g, x, y, z, h, ld);
+            else
+                pull<L, S, false>(src, mask, g, x, y, z, h, ld);
+        }
+    } else {
+        pull<L, S, false>(src, mask, g, x, y, z, h, ld);
+    }
+    C px = C(0), py = C(0), pz = C(0);
+    if (!solid) {
+        C drho, jx, jy, jz;
+        shifted_moments<L>(h, drho, jx, jy, jz);
+        const C rho = C(1) + drho;
+        const C inv = C(1) / rho;
+        const C ux = jx * inv + r.hgx, uy = jy * inv + r.hgy, uz = jz * inv + r.hgz;
+        px = rho * (ux * ux * ux);
+        py = rho * (uy * uy * uy);
+        pz = rho * (uz * uz * uz);
+    }
+    phi[phi_index<C>(g, 0, row, x)] = px;
+    phi[phi_index<C>(g, 1, row, x)] = py;
+    if constexpr (L::D == 3) phi[phi_index<C>(g, 2, row, x)] = pz;
 }
 
 // Fused step kernel.
@@ -213,11 +300,13 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
 // D3Q27 in FP64, launched with at most 256 (row workgroups of 1 KB per
 // direction, or the 64 x 4 fallback): the smaller bound lifts the register
 // cap from 128 to 512 so that its 27 FP64 populations do not spill.
-template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG, int MODEL = MODEL_PTRT>
+template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG, int MODEL = MODEL_PTRT,
+          int FORCING = FORCE_II>
 __global__ void __launch_bounds__((L::Q == 27 && sizeof(S) == 8) ? 256 : 1024)
 k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
        const uint8_t *__restrict__ near, Geom g, Coef<L, typename Codec<S>::compute> r,
-       double2 *__restrict__ partials)
+       double2 *__restrict__ partials,
+       const typename Codec<S>::compute *__restrict__ phi = nullptr)
 {
     int x, y, z;
     if constexpr (ROW) {
@@ -236,13 +325,16 @@ k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict
         if (inside || ROW) {
             if (near[row]) {
                 if (inside && mask[row * (unsigned)g.nx + (unsigned)x] == 0)
-                    node_update<L, S, true, NT, MODEL>(src, dst, mask, g, r, x, y, z, row, m, k);
+                    node_update<L, S, true, NT, MODEL, FORCING>(src, dst, mask, g, r, x, y, z,
+                                                                row, m, k, phi);
             } else if (inside) {
-                node_update<L, S, false, NT, MODEL>(src, dst, mask, g, r, x, y, z, row, m, k);
+                node_update<L, S, false, NT, MODEL, FORCING>(src, dst, mask, g, r, x, y, z, row,
+                                                             m, k, phi);
             }
         }
     } else if (inside) {
-        node_update<L, S, false, NT, MODEL>(src, dst, mask, g, r, x, y, z, row, m, k);
+        node_update<L, S, false, NT, MODEL, FORCING>(src, dst, mask, g, r, x, y, z, row, m, k,
+                                                     phi);
     }
     if constexpr (DIAG) {
         block_sum2(m, k);

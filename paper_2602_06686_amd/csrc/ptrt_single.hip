@@ -7,8 +7,16 @@
 #include <vector>
 
 #include "host_common.hpp"
+#include "step_launch.hpp"
 
 using namespace ptrt;
+
+static_assert(FORCE_II == PTRT_FORCING_SCHEME2 && FORCE_II_G == PTRT_FORCING_SCHEME2_G &&
+                  FORCE_GUO == PTRT_FORCING_GUO,
+              "forcing ids of the kernels and of the C interface");
+static_assert(MODEL_PTRT == PTRT_MODEL_PTRT && MODEL_TRT_RLB == PTRT_MODEL_TRT_RLB &&
+                  MODEL_TRT == PTRT_MODEL_TRT && MODEL_PTRT_EXACT == PTRT_MODEL_PTRT_EXACT,
+              "model ids of the kernels and of the C interface");
 
 namespace {
 
@@ -40,6 +48,8 @@ struct ptrt_ctx {
     bool row_kernel = false, nt_store = false;
     int row_bx = 256;
     int model = MODEL_PTRT;
+    int forcing = FORCE_II;
+    void *d_phi = nullptr; // Phi field of the cubic correction (compute type)
     // small lattices: steps replayed from captured graphs of GRAPH_STEPS launches
     bool use_graph = false;
     hipStream_t capture_stream = nullptr;
@@ -75,6 +85,8 @@ int slab_planes(const ptrt_ctx *c, int per_node_doubles)
     return std::min(s, c->nz);
 }
 
+int ensure_phi(ptrt_ctx *c, int forcing);
+
 int ensure_allocated(ptrt_ctx *c)
 {
     if (c->allocated) return PTRT_OK;
@@ -108,7 +120,7 @@ int ensure_allocated(ptrt_ctx *c)
     HIPCHK(c, hipMalloc(&c->d_partials, sizeof(double2) * (size_t)c->nparts));
     HIPCHK(c, hipMalloc(&c->d_red, 2 * sizeof(double)));
     c->allocated = true;
-    return PTRT_OK;
+    return ensure_phi(c, c->forcing);
 }
 
 Geom geom(const ptrt_ctx *c) { return c->geo; }
@@ -171,7 +183,7 @@ int upload_state(ptrt_ctx *c, const double *rho, const double *u, const double *
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) rc = fail(c, PTRT_EDEVICE, std::string("state upload: ") + hipGetErrorString(e));
     }
-    hipFree(d_in);
+    (void)hipFree(d_in);
     return rc;
 }
 
@@ -225,56 +237,65 @@ int download_state(ptrt_ctx *c, double *rho, double *u, double *f)
         }
     }
     if (u && c->lattice == PTRT_D2Q9) std::memset(u + 2 * (size_t)c->N, 0, (size_t)c->N * sizeof(double));
-    hipFree(d_out);
+    (void)hipFree(d_out);
     return rc;
 }
 
 // Enqueue one fused step on stream s (buffer cur -> cur ^ 1).
 void launch_step(ptrt_ctx *c, hipStream_t s)
 {
-    const Geom g = geom(c);
-    const dim3 block = c->row_kernel ? dim3(c->row_bx, 1, 1) : dim3(64, 4, 1);
-    const dim3 grid = c->row_kernel ? dim3((c->nx + c->row_bx - 1) / c->row_bx, c->ny, c->nz)
-                                    : dim3((c->nx + 63) / 64, (c->ny + 3) / 4, c->nz);
-    const void *src = c->buf[c->cur];
-    void *dst = c->buf[c->cur ^ 1];
-    dispatch(c->lattice, c->storage, c->has_mask, [&](auto lt, auto st, auto mk) -> int {
-        using L = typename decltype(lt)::type;
-        using S = typename decltype(st)::type;
-        using C = typename Codec<S>::compute;
-        constexpr bool M = decltype(mk)::value;
-        const Coef<L, C> r = make_coef<L, C>(c->tau_plus, c->Lambda, c->g);
-        auto go = [&](auto rowc, auto ntc, auto mc) {
-            constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
-            constexpr int MD = decltype(mc)::value;
-            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false, MD>), grid, block, 0, s,
-                               (const S *)src, (S *)dst, c->d_mask, c->d_near, g, r,
-                               (double2 *)nullptr);
-        };
-        using P0 = std::integral_constant<int, MODEL_PTRT>;
-        using P1 = std::integral_constant<int, MODEL_TRT_RLB>;
-        using P2 = std::integral_constant<int, MODEL_TRT>;
-        using P3 = std::integral_constant<int, MODEL_PTRT_EXACT>;
-        auto with_nt = [&](auto rowc, auto mc) {
-            if (c->nt_store) go(rowc, std::true_type{}, mc);
-            else go(rowc, std::false_type{}, mc);
-        };
-        if (!c->row_kernel) {
-            with_nt(std::false_type{}, P0{}); // comparison models need row workgroups
-        } else if (c->model == MODEL_TRT_RLB) {
-            with_nt(std::true_type{}, P1{});
-        } else if (c->model == MODEL_TRT) {
-            with_nt(std::true_type{}, P2{});
-        } else if (c->model == MODEL_PTRT_EXACT) {
-            // the fifth-order modes exist on D3Q27 only; elsewhere it is P-TRT
-            if constexpr (L::Q == 27) with_nt(std::true_type{}, P3{});
-            else with_nt(std::true_type{}, P0{});
-        } else {
-            with_nt(std::true_type{}, P0{});
-        }
-        return PTRT_OK;
-    });
+    StepLaunch a;
+    a.src = c->buf[c->cur];
+    a.dst = c->buf[c->cur ^ 1];
+    a.mask = c->d_mask;
+    a.near = c->d_near;
+    a.g = geom(c);
+    a.tau_plus = c->tau_plus;
+    a.Lambda = c->Lambda;
+    for (int k = 0; k < 3; ++k) a.force[k] = c->g[k];
+    a.storage = c->storage;
+    a.has_mask = c->has_mask;
+    a.row = c->row_kernel;
+    a.row_bx = c->row_bx;
+    a.nt = c->nt_store;
+    a.model = c->model;
+    a.forcing = c->forcing;
+    a.phi = c->d_phi;
+    a.stream = s;
+    if (c->lattice == PTRT_D2Q9) launch_step_d2q9(a);
+    else if (c->lattice == PTRT_D3Q19) launch_step_d3q19(a);
+    else launch_step_d3q27(a);
     c->cur ^= 1;
+}
+
+// Bytes of the Phi field: D components per node in the compute type.
+size_t phi_bytes(const ptrt_ctx *c)
+{
+    const size_t comp = c->storage == PTRT_F64 ? 8 : 4;
+    const size_t D = c->lattice == PTRT_D2Q9 ? 2 : 3;
+    return D * (size_t)c->N * comp;
+}
+
+// Allocate the Phi field once the populations are allocated and the cubic
+// correction is (or is about to be) selected.
+int ensure_phi(ptrt_ctx *c, int forcing)
+{
+    if (forcing != FORCE_II_G || c->d_phi || !c->allocated) return PTRT_OK;
+    hipError_t e = hipMalloc(&c->d_phi, phi_bytes(c));
+    if (e != hipSuccess) {
+        c->d_phi = nullptr;
+        return fail(c, PTRT_ENOMEM, std::string("hipMalloc of the Phi field: ") + hipGetErrorString(e));
+    }
+    return PTRT_OK;
+}
+
+void drop_graphs(ptrt_ctx *c)
+{
+    for (auto &gx : c->graph)
+        if (gx) {
+            (void)hipGraphExecDestroy(gx);
+            gx = nullptr;
+        }
 }
 
 // Capture GRAPH_STEPS steps starting from buffer `parity` into graph[parity].
@@ -291,7 +312,7 @@ int capture_graph(ptrt_ctx *c, int parity)
     c->cur = saved;
     if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&c->graph[parity], gr, nullptr, nullptr, 0);
-    hipGraphDestroy(gr);
+    (void)hipGraphDestroy(gr);
     if (e != hipSuccess) {
         c->graph[parity] = nullptr;
         return fail(c, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -361,14 +382,30 @@ int ptrt_set_model(ptrt_ctx *c, int model)
         return fail(c, PTRT_EINVAL, "unknown collision model");
     if (model != MODEL_PTRT && !c->row_kernel)
         return fail(c, PTRT_EINVAL, "comparison models need ny and nz <= 65535");
+    if (c->forcing != FORCE_II && model != MODEL_PTRT && model != MODEL_PTRT_EXACT)
+        return fail(c, PTRT_EINVAL, "the comparison models use the default forcing only");
     if (hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
     c->model = model;
-    for (auto &gx : c->graph)
-        if (gx) {
-            hipGraphExecDestroy(gx);
-            gx = nullptr;
-        }
+    drop_graphs(c);
+    return PTRT_OK;
+}
+
+int ptrt_set_forcing(ptrt_ctx *c, int forcing)
+{
+    if (!c) return PTRT_EINVAL;
+    if (forcing != FORCE_II && forcing != FORCE_II_G && forcing != FORCE_GUO)
+        return fail(c, PTRT_EINVAL, "unknown forcing scheme");
+    if (forcing != FORCE_II && c->model != MODEL_PTRT && c->model != MODEL_PTRT_EXACT)
+        return fail(c, PTRT_EINVAL, "the comparison models use the default forcing only");
+    if (forcing != FORCE_II && !c->row_kernel)
+        return fail(c, PTRT_EINVAL, "forcing variants need ny and nz <= 65535");
+    if (c->allocated && hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
+    const int rc = ensure_phi(c, forcing);
+    if (rc != PTRT_OK) return rc; // scheme unchanged
+    c->forcing = forcing;
+    drop_graphs(c);
     return PTRT_OK;
 }
 
@@ -407,6 +444,8 @@ int ptrt_step(ptrt_ctx *c, int n)
     if (!c) return PTRT_EINVAL;
     if (n < 0) return fail(c, PTRT_EINVAL, "negative step count");
     if (!c->initialized) return fail(c, PTRT_ESTATE, "ptrt_step before init");
+    if (c->forcing == FORCE_II_G && !c->d_phi)
+        return fail(c, PTRT_ESTATE, "no Phi field for the cubic correction");
     c->t += n;
     if (c->use_graph)
         while (n >= GRAPH_STEPS) {
@@ -483,14 +522,15 @@ int ptrt_destroy(ptrt_ctx *c)
     hipError_t e = hipSuccess;
     if (c->allocated) e = hipStreamSynchronize(c->stream);
     for (int k = 0; k < 2; ++k)
-        if (c->buf[k]) hipFree(c->buf[k]);
-    if (c->d_mask) hipFree(c->d_mask);
-    if (c->d_near) hipFree(c->d_near);
+        if (c->buf[k]) (void)hipFree(c->buf[k]);
+    if (c->d_mask) (void)hipFree(c->d_mask);
+    if (c->d_near) (void)hipFree(c->d_near);
     for (auto &gx : c->graph)
-        if (gx) hipGraphExecDestroy(gx);
-    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
-    if (c->d_partials) hipFree(c->d_partials);
-    if (c->d_red) hipFree(c->d_red);
+        if (gx) (void)hipGraphExecDestroy(gx);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_red) (void)hipFree(c->d_red);
+    if (c->d_phi) (void)hipFree(c->d_phi);
     delete c;
     return e == hipSuccess ? PTRT_OK : PTRT_EDEVICE;
 }

@@ -1,0 +1,8 @@
+// Fused-step kernels of the D3Q19 lattice (one translation unit per lattice).
+#include "step_launch.hpp"
+
+namespace ptrt {
+
+void launch_step_d3q19(const StepLaunch &a) { launch_step_lattice<D3Q19>(a); }
+
+} // namespace ptrt

@@ -1,0 +1,91 @@
+// Launch of one fused step of a single lattice (and, for Scheme II with the
+// cubic correction, the Phi pass before it).  The template is instantiated
+// once per lattice in step_d2q9.hip, step_d3q19.hip and step_d3q27.hip, so
+// the three lattices' kernels compile as separate translation units.
+#pragma once
+
+#include "host_common.hpp"
+
+namespace ptrt {
+
+struct StepLaunch {
+    const void *src = nullptr; // stored state (post-collision at t-1)
+    void *dst = nullptr;       // next state
+    const uint8_t *mask = nullptr, *near = nullptr;
+    Geom g{};
+    double tau_plus = 0, Lambda = 0, force[3] = {0, 0, 0};
+    int storage = PTRT_F32;
+    bool has_mask = false;
+    bool row = true;  // row workgroups of row_bx threads, else 64 x 4 tiles
+    int row_bx = 256;
+    bool nt = false;  // non-temporal stores
+    int model = MODEL_PTRT, forcing = FORCE_II;
+    void *phi = nullptr; // Phi field in the compute type (FORCE_II_G)
+    hipStream_t stream = nullptr;
+};
+
+void launch_step_d2q9(const StepLaunch &a);
+void launch_step_d3q19(const StepLaunch &a);
+void launch_step_d3q27(const StepLaunch &a);
+
+// Model and forcing combinations that have kernels: the comparison models
+// (TRT-RLB, TRT) use Scheme II without G_i; the forcing variants need row
+// workgroups.
+template <class L>
+void launch_step_lattice(const StepLaunch &a)
+{
+    const dim3 block = a.row ? dim3(a.row_bx, 1, 1) : dim3(64, 4, 1);
+    const dim3 grid = a.row ? dim3((a.g.nx + a.row_bx - 1) / a.row_bx, a.g.ny, a.g.nz)
+                            : dim3((a.g.nx + 63) / 64, (a.g.ny + 3) / 4, a.g.nz);
+    dispatch_storage(a.storage, a.has_mask, [&](auto st, auto mk) -> int {
+        using S = typename decltype(st)::type;
+        using C = typename Codec<S>::compute;
+        constexpr bool M = decltype(mk)::value;
+        const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
+        const S *src = (const S *)a.src;
+        S *dst = (S *)a.dst;
+        C *phi = (C *)a.phi;
+        auto go = [&](auto rowc, auto ntc, auto mc, auto fc) {
+            constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
+            constexpr int MD = decltype(mc)::value, FC = decltype(fc)::value;
+            if constexpr (FC == FORCE_II_G)
+                hipLaunchKernelGGL((k_phi<L, S, M, RW>), grid, block, 0, a.stream, src, a.mask,
+                                   a.near, a.g, r, phi);
+            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false, MD, FC>), grid, block, 0, a.stream,
+                               src, dst, a.mask, a.near, a.g, r, (double2 *)nullptr,
+                               (const C *)phi);
+        };
+        auto with_nt = [&](auto rowc, auto mc, auto fc) {
+            if (a.nt) go(rowc, std::true_type{}, mc, fc);
+            else go(rowc, std::false_type{}, mc, fc);
+        };
+        using P0 = std::integral_constant<int, MODEL_PTRT>;
+        using P1 = std::integral_constant<int, MODEL_TRT_RLB>;
+        using P2 = std::integral_constant<int, MODEL_TRT>;
+        using P3 = std::integral_constant<int, MODEL_PTRT_EXACT>;
+        using F0 = std::integral_constant<int, FORCE_II>;
+        using F1 = std::integral_constant<int, FORCE_II_G>;
+        using F2 = std::integral_constant<int, FORCE_GUO>;
+        auto with_forcing = [&](auto mc) {
+            if (a.forcing == FORCE_II_G) with_nt(std::true_type{}, mc, F1{});
+            else if (a.forcing == FORCE_GUO) with_nt(std::true_type{}, mc, F2{});
+            else with_nt(std::true_type{}, mc, F0{});
+        };
+        if (!a.row) {
+            with_nt(std::false_type{}, P0{}, F0{}); // other models / forcings need row workgroups
+        } else if (a.model == MODEL_TRT_RLB) {
+            with_nt(std::true_type{}, P1{}, F0{});
+        } else if (a.model == MODEL_TRT) {
+            with_nt(std::true_type{}, P2{}, F0{});
+        } else if (a.model == MODEL_PTRT_EXACT) {
+            // the fifth-order modes exist on D3Q27 only; elsewhere it is P-TRT
+            if constexpr (L::Q == 27) with_forcing(P3{});
+            else with_forcing(P0{});
+        } else {
+            with_forcing(P0{});
+        }
+        return PTRT_OK;
+    });
+}
+
+} // namespace ptrt

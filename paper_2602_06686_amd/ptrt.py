@@ -25,6 +25,9 @@ PTRT_MODEL_PTRT, PTRT_MODEL_TRT_RLB, PTRT_MODEL_TRT, PTRT_MODEL_PTRT_EXACT = 0, 
 MODEL = {"ptrt": PTRT_MODEL_PTRT, "trt-rlb": PTRT_MODEL_TRT_RLB, "trt": PTRT_MODEL_TRT,
          "ptrt-exact": PTRT_MODEL_PTRT_EXACT}
 STORAGE = {"f64": PTRT_F64, "f32": PTRT_F32, "f16": PTRT_F16, "bf16": PTRT_BF16}
+PTRT_FORCING_SCHEME2, PTRT_FORCING_SCHEME2_G, PTRT_FORCING_GUO = 0, 1, 2
+FORCING = {"scheme2": PTRT_FORCING_SCHEME2, "scheme2+g": PTRT_FORCING_SCHEME2_G,
+           "guo": PTRT_FORCING_GUO}
 Q_OF = {PTRT_D2Q9: 9, PTRT_D3Q19: 19, PTRT_D3Q27: 27}
 
 STATUS = {0: "PTRT_OK", -1: "PTRT_EINVAL", -2: "PTRT_ETAU", -3: "PTRT_ENOMEM",
@@ -58,6 +61,7 @@ _SIGS = {
                                    ctypes.POINTER(_vp)]),
     "ptrt_set_storage": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_model": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_set_forcing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ptrt_init_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
     "ptrt_step": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -163,6 +167,11 @@ def ptrt_set_model(h, model):
     return _check(_lib.ptrt_set_model(h.ptr, model), h.ptr)
 
 
+def ptrt_set_forcing(h, forcing):
+    forcing = FORCING.get(forcing, forcing)
+    return _check(_lib.ptrt_set_forcing(h.ptr, forcing), h.ptr)
+
+
 def ptrt_set_stream(h, stream):
     return _check(_lib.ptrt_set_stream(h.ptr, _stream_handle(stream)), h.ptr)
 
@@ -246,12 +255,14 @@ class Lattice:
     """Convenience owner of one handle: create / init / step / read back."""
 
     def __init__(self, lattice, nx, ny, nz, tau_plus, Lambda, force=None, solid_mask=None,
-                 storage="f32", stream=None, model="ptrt"):
+                 storage="f32", stream=None, model="ptrt", forcing="scheme2"):
         self.h = ptrt_create(lattice, nx, ny, nz, tau_plus, Lambda, force, solid_mask)
         try:
             ptrt_set_storage(self.h, storage)
             if model != "ptrt":
                 ptrt_set_model(self.h, model)
+            if forcing != "scheme2":
+                ptrt_set_forcing(self.h, forcing)
             if stream is not None:
                 ptrt_set_stream(self.h, stream)
         except Exception:

@@ -88,3 +88,20 @@ def test_batch_create_validation():
     assert "instance 0" in P.ptrt_batch_last_error()
     with pytest.raises(P.PtrtError):
         P.ptrt_batch_create([])
+
+
+def test_forcing_validation_without_device():
+    h = P.ptrt_create(0, 8, 8, 1, 0.7, 0.25, force=[1e-5, 0, 0])
+    try:
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_set_forcing(h, 7)
+        assert ei.value.code == -1
+        P.ptrt_set_forcing(h, "guo")
+        P.ptrt_set_forcing(h, "scheme2+g")
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_set_model(h, "trt-rlb")          # comparison models: default forcing only
+        assert ei.value.code == -1
+        P.ptrt_set_forcing(h, "scheme2")
+    finally:
+        P.ptrt_destroy(h)
+    assert P.FORCING == {"scheme2": 0, "scheme2+g": 1, "guo": 2}
