@@ -162,6 +162,32 @@ int ptrt_set_model(ptrt_ctx *ctx, int model);
  * fails.  Default PTRT_FORCING_SCHEME2. */
 int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
 
+/* Open boundaries in x instead of periodic x (Sec. 3.4, creeping flow past
+ * a square cylinder; D2Q9 only).  Inlet: a halfway bounce-back wall at
+ * x = -1/2 moving with velocity (u_in, 0) and density rho_0 = 1; a
+ * population leaving node x = 0 through it returns as
+ * f_ibar = f*_i - 2 w_i rho_0 e_i.u_w / c_s^2.  Outlet: the Zou-He pressure
+ * condition at x = nx - 1 with density rho_out and u_y = 0 sets the three
+ * populations entering through it; populations leaving through it are
+ * dropped.  y stays periodic; solid nodes still bounce back.  Only before
+ * the first init or set_populations (PTRT_ESTATE afterwards); needs nx >= 2,
+ * ny <= 65535, finite u_in, finite rho_out > 0, and a forcing other than
+ * PTRT_FORCING_SCHEME2_G (PTRT_EINVAL otherwise).  With open boundaries the
+ * populations set at the outlet's entering slots are not stored (every
+ * step computes them), so ptrt_get_populations returns the Zou-He values
+ * there. */
+int ptrt_set_open_x(ptrt_ctx *ctx, double u_in, double rho_out);
+
+/* Momentum-exchange force on all solid nodes (Eq. Fx), from the
+ * post-collision state of the last completed step (time t - 1):
+ * force_out[3] = sum over fluid nodes x_f and directions i with x_f + e_i
+ * solid of 2 e_i f*_i(x_f) (halfway bounce-back returns the population that
+ * left, so f*_ibar(x_s) = f*_i(x_f)), in lattice units, FP64.  Links
+ * through open boundaries are not counted.  Zeros without solid nodes.
+ * PTRT_ESTATE before the first step.  Synchronises the handle's stream; the
+ * first call allocates a small reduction buffer owned by the handle. */
+int ptrt_momentum_exchange(ptrt_ctx *ctx, double force_out[3]);
+
 /* Stream for all later work of this handle; a hipStream_t passed as void*
  * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */
 int ptrt_set_stream(ptrt_ctx *ctx, void *hip_stream);

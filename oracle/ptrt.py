@@ -65,6 +65,10 @@ def _load():
                                            ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
                                            ctypes.c_int, ctypes.c_int]
+        lib.ptrt_oracle_run_open.argtypes = lib.ptrt_oracle_run_ex.argtypes + [_dp]
+        lib.ptrt_oracle_momentum_exchange.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp, _dp, _dp]
         lib.ptrt_oracle_phi_gradient.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, _dp, _u8p, _dp, _dp]
         lib.ptrt_oracle_collide_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -196,8 +200,11 @@ class Lattice:
     """
 
     def __init__(self, lat, nx, ny, nz, tau_plus, Lambda, g=None, solid=None,
-                 tau_minus=None, nthreads=0, model=0, forcing=0):
+                 tau_minus=None, nthreads=0, model=0, forcing=0, open_x=None):
         self.lat = lat
+        # open_x = (u_in, rho_out): velocity inlet at x = -1/2 and Zou-He
+        # pressure outlet at x = nx - 1 instead of periodic x (D2Q9)
+        self.open_x = None if open_x is None else np.array(open_x, dtype=np.float64)
         self.model = int(model)  # PTRT, TRT, PTRT_EXACT or PTRT_GHOST
         self.forcing = int(forcing)  # FORCING_II, FORCING_II_G or FORCING_GUO
         self.Q = _Q[lat]
@@ -236,12 +243,28 @@ class Lattice:
     def step(self, n=1):
         nz, ny, nx = self.shape
         solid = _p(self.solid, _u8p) if self.solid is not None else None
-        rc = _load().ptrt_oracle_run_ex(self.lat, self.model, self.forcing, nx, ny, nz,
-                                        self.tau_plus, self.Lambda, self.tau_minus, _p(self.g),
-                                        solid, _p(self.f), int(n), self.nthreads)
+        args = (self.lat, self.model, self.forcing, nx, ny, nz, self.tau_plus, self.Lambda,
+                self.tau_minus, _p(self.g), solid, _p(self.f), int(n), self.nthreads)
+        if self.open_x is None:
+            rc = _load().ptrt_oracle_run_ex(*args)
+        else:
+            rc = _load().ptrt_oracle_run_open(*args, _p(self.open_x))
         if rc != 0:
             raise RuntimeError(f"oracle run failed ({rc})")
         self.t += n
+
+    def momentum_exchange(self):
+        """Force on the solid nodes at the current time (Eq. Fx), [3]."""
+        nz, ny, nx = self.shape
+        F = np.zeros(3)
+        solid = _p(self.solid, _u8p) if self.solid is not None else None
+        rc = _load().ptrt_oracle_momentum_exchange(
+            self.lat, self.model, self.forcing, nx, ny, nz, self.tau_plus, self.Lambda,
+            self.tau_minus, _p(self.g), solid, _p(self.f),
+            _p(self.open_x) if self.open_x is not None else None, _p(F))
+        if rc != 0:
+            raise RuntimeError(f"oracle momentum exchange failed ({rc})")
+        return F
 
     def phi_gradient(self):
         """d_a (rho u_a^3) of the current state at every node, [N,3]."""

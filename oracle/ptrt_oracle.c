@@ -27,6 +27,18 @@
  *     the 2D lattice); the derivative is the central difference
  *     (Phi(x + e_a) - Phi(x - e_a)) / 2 with periodic wrap, and Phi = 0 at
  *     solid nodes (the wall velocity is zero).
+ *  R18 (open boundaries, Sec. 3.4; D2Q9 only).  The inlet x = -1/2 is a
+ *     halfway bounce-back wall moving with u_w = (u_in, 0) and density
+ *     rho_0 = 1: a population leaving node x = 0 through it returns as
+ *     f_ibar = f*_i - 2 w_i rho_0 e_i.u_w / c_s^2.  The outlet x = nx - 1 is
+ *     a Zou-He pressure node (rho = rho_out, u_y = 0): populations leaving
+ *     through it are lost, the three entering ones are
+ *     f_3 = f_1 - (2/3) rho u_x, f_7 = f_5 + (f_2 - f_4)/2 - rho u_x / 6,
+ *     f_6 = f_8 - (f_2 - f_4)/2 - rho u_x / 6, with
+ *     u_x = (f_0 + f_2 + f_4 + 2 (f_1 + f_5 + f_8)) / rho_out - 1.
+ *     y stays periodic.  Momentum exchange (Eq. Fx): on a halfway
+ *     bounce-back wall the population re-entering the fluid equals the one
+ *     that left, so F = sum over fluid-solid links of 2 e_i f*_i(x_f).
  *  R17 (Scheme I, Eq. source_guo).  As printed, the -u.F/c_s^2 part sits
  *     under the tau- factor, so sum_i S_i = (u.F/c_s^2)(1/(2 tau-) -
  *     1/(2 tau+)) and mass is not conserved unless tau+ = tau-.  The
@@ -572,17 +584,62 @@ static void phi_gradient(const Lattice *L, int nx, int ny, int nz, const double 
  * neighbours (R7).  Populations stored at solid nodes are not touched.
  * tau_minus <= 0 means "derive from Lambda".
  */
-int ptrt_oracle_run_ex(int id, int model, int forcing, int nx, int ny, int nz, double tau_plus,
-                       double Lambda, double tau_minus, const double g[3], const uint8_t *solid,
-                       double *f, int nsteps, int nthreads)
+/* Zou-He pressure node on the east side of a D2Q9 lattice (R18): fills the
+ * populations 3, 6, 7 (entering from outside) from the known ones. */
+static void zou_he_outlet(double *f, double rho_out)
 {
-    Lattice L;
-    if (make_lattice(id, &L)) return -1;
+    double ux = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / rho_out - 1.0;
+    f[3] = f[1] - 2.0 / 3.0 * rho_out * ux;
+    f[7] = f[5] + 0.5 * (f[2] - f[4]) - rho_out * ux / 6.0;
+    f[6] = f[8] - 0.5 * (f[2] - f[4]) - rho_out * ux / 6.0;
+}
+
+/* Collide every fluid node of f into fstar (the forcing scheme's Phi field
+ * computed from f first when needed). */
+static void collide_all(const Lattice *L, int model, int forcing, int nx, int ny, int nz,
+                        double tau_plus, double tau_m, const double g[3], const uint8_t *solid,
+                        const double *f, double *fstar, double *phi)
+{
+    size_t N = (size_t)nx * ny * nz;
+    int Q = L->Q;
+    if (phi) phi_field(L, N, f, g, solid, phi);
+#pragma omp parallel for schedule(static)
+    for (long long m = 0; m < (long long)N; ++m) {
+        if (solid && solid[m]) continue;
+        double dphi[3] = {0.0, 0.0, 0.0};
+        if (phi) phi_gradient(L, nx, ny, nz, phi, (size_t)m, dphi);
+        collide_full(L, f + m * Q, g, tau_plus, tau_m, model, forcing, dphi, fstar + m * Q);
+    }
+}
+
+static int check_run_args(int id, int model, int forcing, int nz, const double *open)
+{
     if (id == 0 && nz != 1) return -2;
     if (model != MODEL_PTRT && model != MODEL_TRT && model != MODEL_PTRT_EXACT &&
         model != MODEL_PTRT_GHOST)
         return -4;
     if (forcing != FORCING_II && forcing != FORCING_II_G && forcing != FORCING_GUO) return -5;
+    if (open && (id != 0 || forcing == FORCING_II_G || !(open[1] > 0.0))) return -6;
+    return 0;
+}
+
+/*
+ * Advance f [N][Q] (pre-collision populations at time t) by nsteps steps:
+ * collide every fluid node (Eq. PTRT, R1; the forcing scheme as selected),
+ * then stream with periodic wrap and halfway bounce-back at solid
+ * neighbours (R7).  Populations stored at solid nodes are not touched.
+ * tau_minus <= 0 means "derive from Lambda".  open = {u_in, rho_out}
+ * replaces the x-periodicity by the inlet and outlet of R18 (D2Q9), NULL
+ * keeps every direction periodic.
+ */
+static int run_impl(int id, int model, int forcing, int nx, int ny, int nz, double tau_plus,
+                    double Lambda, double tau_minus, const double g[3], const uint8_t *solid,
+                    double *f, int nsteps, int nthreads, const double *open)
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    int rc = check_run_args(id, model, forcing, nz, open);
+    if (rc) return rc;
     double tau_m = tau_minus > 0.0 ? tau_minus : tau_minus_from_lambda(tau_plus, Lambda);
     int Q = L.Q;
     size_t N = (size_t)nx * ny * nz;
@@ -598,32 +655,103 @@ int ptrt_oracle_run_ex(int id, int model, int forcing, int nx, int ny, int nz, d
 #else
     (void)nthreads;
 #endif
+    const double rho_w = 1.0; /* rho_0 of the moving inlet wall (R18) */
     for (int step = 0; step < nsteps; ++step) {
-        if (phi) phi_field(&L, N, f, g, solid, phi);
-        /* collision */
-#pragma omp parallel for schedule(static)
-        for (long long m = 0; m < (long long)N; ++m) {
-            if (solid && solid[m]) continue;
-            double dphi[3] = {0.0, 0.0, 0.0};
-            if (phi) phi_gradient(&L, nx, ny, nz, phi, (size_t)m, dphi);
-            collide_full(&L, f + m * Q, g, tau_plus, tau_m, model, forcing, dphi, fstar + m * Q);
-        }
+        collide_all(&L, model, forcing, nx, ny, nz, tau_plus, tau_m, g, solid, f, fstar, phi);
         /* streaming, left side of Eq. PTRT, with halfway bounce-back */
 #pragma omp parallel for schedule(static)
         for (long long m = 0; m < (long long)N; ++m) {
             if (solid && solid[m]) continue;
             int x = (int)(m % nx), y = (int)((m / nx) % ny), z = (int)(m / ((size_t)nx * ny));
             for (int i = 0; i < Q; ++i) {
+                double fs = fstar[(size_t)m * Q + i];
+                if (open && x + L.e[i][0] < 0) { /* through the moving inlet wall */
+                    double eu = L.e[i][0] * open[0];
+                    f[(size_t)m * Q + L.opp[i]] = fs - 2.0 * L.w[i] * rho_w * eu / L.cs2;
+                    continue;
+                }
+                if (open && x + L.e[i][0] >= nx) continue; /* leaves through the outlet */
                 int xn = wrap(x + L.e[i][0], nx), yn = wrap(y + L.e[i][1], ny),
                     zn = wrap(z + L.e[i][2], nz);
                 size_t t = node_index(xn, yn, zn, nx, ny);
                 if (solid && solid[t])
-                    f[(size_t)m * Q + L.opp[i]] = fstar[(size_t)m * Q + i];
+                    f[(size_t)m * Q + L.opp[i]] = fs;
                 else
-                    f[t * Q + i] = fstar[(size_t)m * Q + i];
+                    f[t * Q + i] = fs;
             }
         }
+        if (open)
+            for (int y = 0; y < ny; ++y) {
+                size_t m = node_index(nx - 1, y, 0, nx, ny);
+                if (!(solid && solid[m])) zou_he_outlet(f + m * Q, open[1]);
+            }
     }
+    free(fstar);
+    free(phi);
+    return 0;
+}
+
+int ptrt_oracle_run_ex(int id, int model, int forcing, int nx, int ny, int nz, double tau_plus,
+                       double Lambda, double tau_minus, const double g[3], const uint8_t *solid,
+                       double *f, int nsteps, int nthreads)
+{
+    return run_impl(id, model, forcing, nx, ny, nz, tau_plus, Lambda, tau_minus, g, solid, f,
+                    nsteps, nthreads, NULL);
+}
+
+/* The same with the open boundaries of R18 (D2Q9): open = {u_in, rho_out}. */
+int ptrt_oracle_run_open(int id, int model, int forcing, int nx, int ny, int nz, double tau_plus,
+                         double Lambda, double tau_minus, const double g[3],
+                         const uint8_t *solid, double *f, int nsteps, int nthreads,
+                         const double *open)
+{
+    if (!open) return -6;
+    return run_impl(id, model, forcing, nx, ny, nz, tau_plus, Lambda, tau_minus, g, solid, f,
+                    nsteps, nthreads, open);
+}
+
+/* Momentum-exchange force on the solid nodes at time t (Eq. Fx, R18):
+ * collide the pre-collision state f at t, then F = sum over fluid nodes x_f
+ * and directions i with x_f + e_i solid of 2 e_i f*_i(x_f).  open != NULL:
+ * links through the inlet and outlet are not solid links. */
+int ptrt_oracle_momentum_exchange(int id, int model, int forcing, int nx, int ny, int nz,
+                                  double tau_plus, double Lambda, double tau_minus,
+                                  const double g[3], const uint8_t *solid, const double *f,
+                                  const double *open, double F[3])
+{
+    Lattice L;
+    if (make_lattice(id, &L)) return -1;
+    int rc = check_run_args(id, model, forcing, nz, open);
+    if (rc) return rc;
+    double tau_m = tau_minus > 0.0 ? tau_minus : tau_minus_from_lambda(tau_plus, Lambda);
+    int Q = L.Q;
+    size_t N = (size_t)nx * ny * nz;
+    double *fstar = (double *)malloc(N * Q * sizeof(double));
+    double *phi = forcing == FORCING_II_G ? (double *)malloc(N * 3 * sizeof(double)) : NULL;
+    if (!fstar || (forcing == FORCING_II_G && !phi)) {
+        free(fstar);
+        free(phi);
+        return -3;
+    }
+    collide_all(&L, model, forcing, nx, ny, nz, tau_plus, tau_m, g, solid, f, fstar, phi);
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    for (size_t m = 0; m < N; ++m) {
+        if (!solid || solid[m]) continue;
+        int x = (int)(m % nx), y = (int)((m / nx) % ny), z = (int)(m / ((size_t)nx * ny));
+        for (int i = 1; i < Q; ++i) {
+            if (open && (x + L.e[i][0] < 0 || x + L.e[i][0] >= nx)) continue;
+            size_t t = node_index(wrap(x + L.e[i][0], nx), wrap(y + L.e[i][1], ny),
+                                  wrap(z + L.e[i][2], nz), nx, ny);
+            if (!solid[t]) continue;
+            double fs = fstar[m * Q + i];
+            Fx += 2.0 * L.e[i][0] * fs;
+            Fy += 2.0 * L.e[i][1] * fs;
+            Fz += 2.0 * L.e[i][2] * fs;
+        }
+    }
+    F[0] = Fx;
+    F[1] = Fy;
+    F[2] = Fz;
     free(fstar);
     free(phi);
     return 0;

@@ -34,6 +34,10 @@ struct Geom {
     int lr;          // log2 of rows per tile
     long long plane; // elements of one direction inside a tile: nx << lr
     long long tile;  // elements of a tile: Q * plane
+    // Open boundaries in x (D2Q9, kernels with OPEN = true only): inlet wall
+    // at x = -1/2 moving with (uin, 0), pressure outlet rho = 1 + drhoout at
+    // x = nx - 1.
+    double uin = 0.0, drhoout = 0.0;
 };
 
 // Offset of the first element of direction q of a row; element (q, row, x)
@@ -77,8 +81,36 @@ __device__ __forceinline__ void source_of(const Geom &g, const Nbr &n, int x, in
     srow = (unsigned)sz * (unsigned)g.ny + (unsigned)sy;
 }
 
+// Zou-He pressure node on the east side of D2Q9 (x = nx - 1, u_y = 0), in
+// shifted populations: the three populations entering from outside
+// (3: (-1,0), 6: (-1,1), 7: (-1,-1)) from the six known ones and
+// rho_out = 1 + drho_out:
+//   rho_out u_x = h0 + h2 + h4 + 2 (h1 + h5 + h8) - drho_out,
+//   h3 = h1 - (2/3) rho_out u_x,
+//   h7 = h5 + (h2 - h4)/2 - rho_out u_x / 6,  h6 = h8 - (h2 - h4)/2 - rho_out u_x / 6
+// (the shifts w_i cancel pairwise and sum to 1 in the first line).
+template <class T>
+__device__ __forceinline__ void zou_he_east(T (&h)[9], T drho_out)
+{
+    static_assert(D2Q9::ex(1) == 1 && D2Q9::ex(3) == -1 && D2Q9::ey(2) == 1 && D2Q9::ey(4) == -1 &&
+                      D2Q9::ex(5) == 1 && D2Q9::ey(5) == 1 && D2Q9::ex(6) == -1 &&
+                      D2Q9::ey(6) == 1 && D2Q9::ex(7) == -1 && D2Q9::ey(7) == -1 &&
+                      D2Q9::ex(8) == 1 && D2Q9::ey(8) == -1,
+                  "D2Q9 velocity order");
+    const T ru = (h[0] + h[2] + h[4] + T(2) * (h[1] + h[5] + h[8])) - drho_out;
+    const T d = T(0.5) * (h[2] - h[4]);
+    h[3] = h[1] - T(2.0 / 3.0) * ru;
+    h[7] = h[5] + d - T(1.0 / 6.0) * ru;
+    h[6] = h[8] - d - T(1.0 / 6.0) * ru;
+}
+
 // Pull the Q populations of fluid node (x, y, z) into registers (type T).
-template <class L, class S, bool MASK, class T, class LoadF>
+// OPEN (D2Q9): x is not periodic; at x = 0 the populations entering through
+// the inlet wall are the node's own outgoing ones plus 2 w_i e_i.u_w / c_s^2
+// (moving halfway bounce-back, rho_0 = 1); at x = nx - 1 the populations
+// entering through the outlet come from zou_he_east.  The periodic loads
+// of those populations stay in bounds and are overwritten.
+template <class L, class S, bool MASK, bool OPEN = false, class T, class LoadF>
 __device__ __forceinline__ void pull(const S *__restrict__ src, const uint8_t *__restrict__ mask,
                                      const Geom &g, int x, int y, int z, T (&h)[L::Q], LoadF load)
 {
@@ -102,11 +134,24 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const uint8_t *_
             }
         }
     });
+    if constexpr (OPEN) {
+        static_assert(L::D == 2 && L::Q == 9, "open boundaries are built for D2Q9");
+        if (x == 0) {
+            static_for<L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (L::ex(i) == 1)
+                    h[i] = load(at(src, g, L::opp(i), row, x)) + T(6.0 * L::w(i)) * T(g.uin);
+            });
+        }
+        if (x == g.nx - 1) zou_he_east(h, T(g.drhoout));
+    }
 }
 
 // Write the pre-collision populations hv (shifted, FP64) of a fluid node into
 // the slots its next pull reads: the inverse of pull().
-template <class L, class S, bool MASK>
+// OPEN: the inlet slots take hv minus the wall-velocity term; the outlet's
+// entering populations are computed by every pull and are not stored.
+template <class L, class S, bool MASK, bool OPEN = false>
 __device__ __forceinline__ void scatter(S *__restrict__ dst, const uint8_t *__restrict__ mask,
                                         const Geom &g, int x, int y, int z, const double (&hv)[L::Q])
 {
@@ -116,6 +161,10 @@ __device__ __forceinline__ void scatter(S *__restrict__ dst, const uint8_t *__re
         constexpr int i = decltype(ic)::value;
         if constexpr (i == 0) {
             store_f64(at(dst, g, 0, row, x), hv[0]);
+        } else if (OPEN && L::ex(i) == 1 && x == 0) {
+            store_f64(at(dst, g, L::opp(i), row, x), hv[i] - 6.0 * L::w(i) * g.uin);
+        } else if (OPEN && L::ex(i) == -1 && x == g.nx - 1) {
+            // filled by the outlet condition on every pull
         } else {
             int sx;
             unsigned srow;
@@ -202,7 +251,8 @@ __device__ __forceinline__ Src<C> phi_differences(const C *__restrict__ phi, con
 // ---------------------------------------------------------------------------
 // One node update: pull, moments, equilibrium, parity split, ghost removal,
 // two-rate relaxation, force; store to the node's own slots of dst.
-template <class L, class S, bool MASK, bool NT, int MODEL = MODEL_PTRT, int FORCING = FORCE_II>
+template <class L, class S, bool MASK, bool NT, int MODEL = MODEL_PTRT, int FORCING = FORCE_II,
+          bool OPEN = false>
 __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__restrict__ dst,
                                             const uint8_t *__restrict__ mask, const Geom &g,
                                             const Coef<L, typename Codec<S>::compute> &r, int x,
@@ -214,7 +264,7 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
     static_assert(MODEL != MODEL_TRT_RLB || FORCING == FORCE_II,
                   "the TRT-RLB comparison kernel uses Scheme II only");
     C h[L::Q];
-    pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
+    pull<L, S, MASK, OPEN>(src, mask, g, x, y, z, h, [](const S *p) { return Codec<S>::load(p); });
     Src<C> sc{};
     if constexpr (FORCING == FORCE_II_G) sc = phi_differences<L, C>(phi, g, r, x, y, z, row);
     C rho, ux, uy, uz;
@@ -301,7 +351,7 @@ k_phi(const S *__restrict__ src, const uint8_t *__restrict__ mask, const uint8_t
 // direction, or the 64 x 4 fallback): the smaller bound lifts the register
 // cap from 128 to 512 so that its 27 FP64 populations do not spill.
 template <class L, class S, bool MASK, bool ROW, bool NT, bool DIAG, int MODEL = MODEL_PTRT,
-          int FORCING = FORCE_II>
+          int FORCING = FORCE_II, bool OPEN = false>
 __global__ void __launch_bounds__((L::Q == 27 && sizeof(S) == 8) ? 256 : 1024)
 k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
        const uint8_t *__restrict__ near, Geom g, Coef<L, typename Codec<S>::compute> r,
@@ -325,16 +375,16 @@ k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict
         if (inside || ROW) {
             if (near[row]) {
                 if (inside && mask[row * (unsigned)g.nx + (unsigned)x] == 0)
-                    node_update<L, S, true, NT, MODEL, FORCING>(src, dst, mask, g, r, x, y, z,
-                                                                row, m, k, phi);
+                    node_update<L, S, true, NT, MODEL, FORCING, OPEN>(src, dst, mask, g, r, x, y,
+                                                                      z, row, m, k, phi);
             } else if (inside) {
-                node_update<L, S, false, NT, MODEL, FORCING>(src, dst, mask, g, r, x, y, z, row,
-                                                             m, k, phi);
+                node_update<L, S, false, NT, MODEL, FORCING, OPEN>(src, dst, mask, g, r, x, y, z,
+                                                                   row, m, k, phi);
             }
         }
     } else if (inside) {
-        node_update<L, S, false, NT, MODEL, FORCING>(src, dst, mask, g, r, x, y, z, row, m, k,
-                                                     phi);
+        node_update<L, S, false, NT, MODEL, FORCING, OPEN>(src, dst, mask, g, r, x, y, z, row, m,
+                                                           k, phi);
     }
     if constexpr (DIAG) {
         block_sum2(m, k);
@@ -344,7 +394,7 @@ k_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict
 
 // ---------------------------------------------------------------------------
 // Scatter a full FP64 state f[Q][N] (unshifted) into dst (pre-collision at t).
-template <class L, class S, bool MASK>
+template <class L, class S, bool MASK, bool OPEN = false>
 __global__ void __launch_bounds__(256)
 k_set_state(S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g, int z0,
             const double *__restrict__ f, long long fstride)
@@ -361,12 +411,12 @@ k_set_state(S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g, int z
         constexpr int i = decltype(ic)::value;
         hv[i] = f[(long long)i * fstride + in] - L::w(i);
     });
-    scatter<L, S, MASK>(dst, mask, g, x, y, z, hv);
+    scatter<L, S, MASK, OPEN>(dst, mask, g, x, y, z, hv);
 }
 
 // Equilibrium initialisation (Eq. feq) in FP64 from rho[N] and u[3][N]
 // (either may be null: rho = 1, u = 0), scattered into dst.
-template <class L, class S, bool MASK>
+template <class L, class S, bool MASK, bool OPEN = false>
 __global__ void __launch_bounds__(256)
 k_init_eq(S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g, int z0,
           const double *__restrict__ rho_in, const double *__restrict__ u_in, long long ustride)
@@ -393,14 +443,14 @@ k_init_eq(S *__restrict__ dst, const uint8_t *__restrict__ mask, Geom g, int z0,
         const double poly = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu + 4.5 * eu * (eu * eu - uu);
         hv[i] = L::w(i) * ((rho - 1.0) + rho * poly);
     });
-    scatter<L, S, MASK>(dst, mask, g, x, y, z, hv);
+    scatter<L, S, MASK, OPEN>(dst, mask, g, x, y, z, hv);
 }
 
 // ---------------------------------------------------------------------------
 // Gather the pre-collision state at t: any of rho[N], u[3][N], f[Q][N]
 // (unshifted) and per-block (mass, kinetic energy) partials.  Solid nodes
 // report zeros and contribute nothing.
-template <class L, class S, bool MASK>
+template <class L, class S, bool MASK, bool OPEN = false>
 __global__ void __launch_bounds__(256)
 k_gather(const S *__restrict__ src, const uint8_t *__restrict__ mask, Geom g, int z0, double gx,
          double gy, double gz, double *__restrict__ rho_out, double *__restrict__ u_out,
@@ -416,7 +466,7 @@ k_gather(const S *__restrict__ src, const uint8_t *__restrict__ mask, Geom g, in
     double m = 0.0, k = 0.0;
     if (fluid) {
         double h[L::Q];
-        pull<L, S, MASK>(src, mask, g, x, y, z, h, [](const S *p) { return load_f64(p); });
+        pull<L, S, MASK, OPEN>(src, mask, g, x, y, z, h, [](const S *p) { return load_f64(p); });
         double drho, jx, jy, jz;
         shifted_moments<L>(h, drho, jx, jy, jz);
         const double rho = 1.0 + drho;
@@ -469,6 +519,91 @@ k_finalize(const double2 *__restrict__ partials, int nparts, double *__restrict_
     if (threadIdx.x == 0) {
         out[0] = a;
         out[1] = b;
+    }
+}
+
+// Sum (a, b, c) over a workgroup of up to 1024 threads; valid in thread 0.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
+{
+    __shared__ double sc[16];
+    block_sum2(a, b);
+    __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wid = tid >> 6, nw = (nthreads + 63) >> 6;
+    if (lane == 0) sc[wid] = c;
+    __syncthreads();
+    if (wid == 0) {
+        c = lane < nw ? sc[lane] : 0.0;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    }
+}
+
+// Momentum-exchange force on the solid nodes (Eq. Fx) from the stored
+// post-collision state of the last step: sum over fluid nodes x_f and
+// directions i with x_f + e_i solid of 2 e_i f*_i(x_f) (on a halfway
+// bounce-back wall the population re-entering the fluid equals the one that
+// left).  Rows without solid neighbours are skipped.  Per-block partials
+// [nblocks][3]; OPEN: links through the inlet and outlet are not wall links.
+template <class L, class S, bool OPEN>
+__global__ void __launch_bounds__(256)
+k_momentum_exchange(const S *__restrict__ src, const uint8_t *__restrict__ mask,
+                    const uint8_t *__restrict__ near, Geom g, double *__restrict__ partials)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (x < g.nx && y < g.ny) {
+        const unsigned row = (unsigned)z * (unsigned)g.ny + (unsigned)y;
+        if (near[row] && !mask[row * (unsigned)g.nx + (unsigned)x]) {
+            const Nbr n(g, x, y, z);
+            static_for<L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (i != 0) {
+                    const bool outside = OPEN && ((L::ex(i) == -1 && x == 0) ||
+                                                  (L::ex(i) == 1 && x == g.nx - 1));
+                    const int tx = L::ex(i) == 1 ? n.xp : (L::ex(i) == -1 ? n.xm : x);
+                    const int ty = L::ey(i) == 1 ? n.yp : (L::ey(i) == -1 ? n.ym : y);
+                    const int tz = L::ez(i) == 1 ? n.zp : (L::ez(i) == -1 ? n.zm : z);
+                    const unsigned trow = (unsigned)tz * (unsigned)g.ny + (unsigned)ty;
+                    if (!outside && mask[trow * (unsigned)g.nx + (unsigned)tx]) {
+                        const double f = load_f64(at(src, g, i, row, x)) + L::w(i);
+                        fx += 2.0 * L::ex(i) * f;
+                        fy += 2.0 * L::ey(i) * f;
+                        fz += 2.0 * L::ez(i) * f;
+                    }
+                }
+            });
+        }
+    }
+    block_sum3(fx, fy, fz);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        const unsigned b = flat_block();
+        partials[3 * (size_t)b] = fx;
+        partials[3 * (size_t)b + 1] = fy;
+        partials[3 * (size_t)b + 2] = fz;
+    }
+}
+
+template <int BLOCK = 1024>
+__global__ void __launch_bounds__(BLOCK)
+k_finalize3(const double *__restrict__ partials, int nparts, double *__restrict__ out)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a += partials[3 * (size_t)i];
+        b += partials[3 * (size_t)i + 1];
+        c += partials[3 * (size_t)i + 2];
+    }
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+        out[2] = c;
     }
 }
 

@@ -50,6 +50,8 @@ struct ptrt_ctx {
     int model = MODEL_PTRT;
     int forcing = FORCE_II;
     void *d_phi = nullptr; // Phi field of the cubic correction (compute type)
+    bool open = false;     // D2Q9 velocity inlet / pressure outlet in x
+    double *d_force_parts = nullptr, *d_force = nullptr; // momentum exchange
     // small lattices: steps replayed from captured graphs of GRAPH_STEPS launches
     bool use_graph = false;
     hipStream_t capture_stream = nullptr;
@@ -71,6 +73,20 @@ int fail(ptrt_ctx *c, int code, const std::string &msg)
         if (e_ != hipSuccess)                                                                \
             return fail((c), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// f(bool_constant<OPEN>) for the handle's x boundaries (open ones exist on
+// D2Q9 only).
+template <class L, class F>
+void with_open(const ptrt_ctx *c, F &&f)
+{
+    if constexpr (L::Q == 9) {
+        if (c->open) {
+            f(std::true_type{});
+            return;
+        }
+    }
+    f(std::false_type{});
+}
 
 dim3 gather_grid(const ptrt_ctx *c, int nzs)
 {
@@ -171,12 +187,15 @@ int upload_state(ptrt_ctx *c, const double *rho, const double *u, const double *
             using L = typename decltype(lt)::type;
             using S = typename decltype(st)::type;
             constexpr bool M = decltype(mk)::value;
-            if (pops)
-                hipLaunchKernelGGL((k_set_state<L, S, M>), grid, block, 0, c->stream, (S *)dst,
-                                   c->d_mask, g, z0, d_in, cnt);
-            else
-                hipLaunchKernelGGL((k_init_eq<L, S, M>), grid, block, 0, c->stream, (S *)dst,
-                                   c->d_mask, g, z0, d_rho, d_u, cnt);
+            with_open<L>(c, [&](auto oc) {
+                constexpr bool O = decltype(oc)::value;
+                if (pops)
+                    hipLaunchKernelGGL((k_set_state<L, S, M, O>), grid, block, 0, c->stream,
+                                       (S *)dst, c->d_mask, g, z0, d_in, cnt);
+                else
+                    hipLaunchKernelGGL((k_init_eq<L, S, M, O>), grid, block, 0, c->stream,
+                                       (S *)dst, c->d_mask, g, z0, d_rho, d_u, cnt);
+            });
             return PTRT_OK;
         });
         e = hipGetLastError();
@@ -210,9 +229,12 @@ int download_state(ptrt_ctx *c, double *rho, double *u, double *f)
             using L = typename decltype(lt)::type;
             using S = typename decltype(st)::type;
             constexpr bool M = decltype(mk)::value;
-            hipLaunchKernelGGL((k_gather<L, S, M>), grid, block, 0, c->stream, (const S *)src,
-                               c->d_mask, g, z0, c->g[0], c->g[1], c->g[2], d_rho, d_u, d_f, cnt,
-                               (double2 *)nullptr);
+            with_open<L>(c, [&](auto oc) {
+                constexpr bool O = decltype(oc)::value;
+                hipLaunchKernelGGL((k_gather<L, S, M, O>), grid, block, 0, c->stream,
+                                   (const S *)src, c->d_mask, g, z0, c->g[0], c->g[1], c->g[2],
+                                   d_rho, d_u, d_f, cnt, (double2 *)nullptr);
+            });
             return PTRT_OK;
         });
         hipError_t e = hipGetLastError();
@@ -261,6 +283,7 @@ void launch_step(ptrt_ctx *c, hipStream_t s)
     a.model = c->model;
     a.forcing = c->forcing;
     a.phi = c->d_phi;
+    a.open = c->open;
     a.stream = s;
     if (c->lattice == PTRT_D2Q9) launch_step_d2q9(a);
     else if (c->lattice == PTRT_D3Q19) launch_step_d3q19(a);
@@ -391,11 +414,64 @@ int ptrt_set_model(ptrt_ctx *c, int model)
     return PTRT_OK;
 }
 
+int ptrt_set_open_x(ptrt_ctx *c, double u_in, double rho_out)
+{
+    if (!c) return PTRT_EINVAL;
+    if (c->lattice != PTRT_D2Q9) return fail(c, PTRT_EINVAL, "open boundaries are built for D2Q9");
+    if (c->nx < 2) return fail(c, PTRT_EINVAL, "open boundaries need nx >= 2");
+    if (!c->row_kernel) return fail(c, PTRT_EINVAL, "open boundaries need ny <= 65535");
+    if (!std::isfinite(u_in) || !std::isfinite(rho_out) || !(rho_out > 0.0))
+        return fail(c, PTRT_EINVAL, "u_in must be finite and rho_out finite and positive");
+    if (c->forcing == FORCE_II_G)
+        return fail(c, PTRT_EINVAL, "the cubic correction needs periodic x");
+    if (c->allocated) return fail(c, PTRT_ESTATE, "open boundaries can only be set before the first init");
+    c->open = true;
+    c->geo.uin = u_in;
+    c->geo.drhoout = rho_out - 1.0;
+    return PTRT_OK;
+}
+
+int ptrt_momentum_exchange(ptrt_ctx *c, double force_out[3])
+{
+    if (!c || !force_out) return PTRT_EINVAL;
+    if (!c->initialized || c->t == 0)
+        return fail(c, PTRT_ESTATE, "momentum exchange needs a completed step");
+    for (int a = 0; a < 3; ++a) force_out[a] = 0.0;
+    if (!c->has_mask) return PTRT_OK;
+    const dim3 grid = gather_grid(c, c->nz), block(BLK_X, BLK_Y, 1);
+    const int nparts = grid.x * grid.y * grid.z;
+    if (!c->d_force_parts) {
+        HIPCHK(c, hipMalloc(&c->d_force_parts, 3 * sizeof(double) * (size_t)nparts));
+        HIPCHK(c, hipMalloc(&c->d_force, 3 * sizeof(double)));
+    }
+    const Geom g = geom(c);
+    const void *src = c->buf[c->cur];
+    dispatch(c->lattice, c->storage, false, [&](auto lt, auto st, auto) -> int {
+        using L = typename decltype(lt)::type;
+        using S = typename decltype(st)::type;
+        with_open<L>(c, [&](auto oc) {
+            constexpr bool O = decltype(oc)::value;
+            hipLaunchKernelGGL((k_momentum_exchange<L, S, O>), grid, block, 0, c->stream,
+                               (const S *)src, c->d_mask, c->d_near, g, c->d_force_parts);
+        });
+        return PTRT_OK;
+    });
+    hipLaunchKernelGGL(k_finalize3<1024>, dim3(1), dim3(1024), 0, c->stream, c->d_force_parts,
+                       nparts, c->d_force);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(force_out, c->d_force, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTRT_OK;
+}
+
 int ptrt_set_forcing(ptrt_ctx *c, int forcing)
 {
     if (!c) return PTRT_EINVAL;
     if (forcing != FORCE_II && forcing != FORCE_II_G && forcing != FORCE_GUO)
         return fail(c, PTRT_EINVAL, "unknown forcing scheme");
+    if (forcing == FORCE_II_G && c->open)
+        return fail(c, PTRT_EINVAL, "the cubic correction needs periodic x");
     if (forcing != FORCE_II && c->model != MODEL_PTRT && c->model != MODEL_PTRT_EXACT)
         return fail(c, PTRT_EINVAL, "the comparison models use the default forcing only");
     if (forcing != FORCE_II && !c->row_kernel)
@@ -487,9 +563,12 @@ int ptrt_diagnostics(ptrt_ctx *c, double *mass, double *ke)
         using L = typename decltype(lt)::type;
         using S = typename decltype(st)::type;
         constexpr bool M = decltype(mk)::value;
-        hipLaunchKernelGGL((k_gather<L, S, M>), grid, block, 0, c->stream, (const S *)src, c->d_mask,
-                           g, 0, c->g[0], c->g[1], c->g[2], (double *)nullptr, (double *)nullptr,
-                           (double *)nullptr, 0LL, c->d_partials);
+        with_open<L>(c, [&](auto oc) {
+            constexpr bool O = decltype(oc)::value;
+            hipLaunchKernelGGL((k_gather<L, S, M, O>), grid, block, 0, c->stream, (const S *)src,
+                               c->d_mask, g, 0, c->g[0], c->g[1], c->g[2], (double *)nullptr,
+                               (double *)nullptr, (double *)nullptr, 0LL, c->d_partials);
+        });
         return PTRT_OK;
     });
     hipLaunchKernelGGL(k_finalize<1024>, dim3(1), dim3(1024), 0, c->stream, c->d_partials, c->nparts, c->d_red);
@@ -531,6 +610,8 @@ int ptrt_destroy(ptrt_ctx *c)
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_red) (void)hipFree(c->d_red);
     if (c->d_phi) (void)hipFree(c->d_phi);
+    if (c->d_force_parts) (void)hipFree(c->d_force_parts);
+    if (c->d_force) (void)hipFree(c->d_force);
     delete c;
     return e == hipSuccess ? PTRT_OK : PTRT_EDEVICE;
 }

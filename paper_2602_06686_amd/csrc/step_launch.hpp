@@ -21,6 +21,7 @@ struct StepLaunch {
     bool nt = false;  // non-temporal stores
     int model = MODEL_PTRT, forcing = FORCE_II;
     void *phi = nullptr; // Phi field in the compute type (FORCE_II_G)
+    bool open = false;   // D2Q9 inlet / outlet in x (values in g)
     hipStream_t stream = nullptr;
 };
 
@@ -29,8 +30,8 @@ void launch_step_d3q19(const StepLaunch &a);
 void launch_step_d3q27(const StepLaunch &a);
 
 // Model and forcing combinations that have kernels: the comparison models
-// (TRT-RLB, TRT) use Scheme II without G_i; the forcing variants need row
-// workgroups.
+// (TRT-RLB, TRT) use Scheme II without G_i; the forcing variants and the
+// open boundaries (D2Q9, not with G_i) need row workgroups.
 template <class L>
 void launch_step_lattice(const StepLaunch &a)
 {
@@ -45,19 +46,16 @@ void launch_step_lattice(const StepLaunch &a)
         const S *src = (const S *)a.src;
         S *dst = (S *)a.dst;
         C *phi = (C *)a.phi;
-        auto go = [&](auto rowc, auto ntc, auto mc, auto fc) {
+        auto go = [&](auto rowc, auto ntc, auto mc, auto fc, auto oc) {
             constexpr bool RW = decltype(rowc)::value, NT = decltype(ntc)::value;
             constexpr int MD = decltype(mc)::value, FC = decltype(fc)::value;
+            constexpr bool OP = decltype(oc)::value;
             if constexpr (FC == FORCE_II_G)
                 hipLaunchKernelGGL((k_phi<L, S, M, RW>), grid, block, 0, a.stream, src, a.mask,
                                    a.near, a.g, r, phi);
-            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false, MD, FC>), grid, block, 0, a.stream,
-                               src, dst, a.mask, a.near, a.g, r, (double2 *)nullptr,
+            hipLaunchKernelGGL((k_step<L, S, M, RW, NT, false, MD, FC, OP>), grid, block, 0,
+                               a.stream, src, dst, a.mask, a.near, a.g, r, (double2 *)nullptr,
                                (const C *)phi);
-        };
-        auto with_nt = [&](auto rowc, auto mc, auto fc) {
-            if (a.nt) go(rowc, std::true_type{}, mc, fc);
-            else go(rowc, std::false_type{}, mc, fc);
         };
         using P0 = std::integral_constant<int, MODEL_PTRT>;
         using P1 = std::integral_constant<int, MODEL_TRT_RLB>;
@@ -66,23 +64,41 @@ void launch_step_lattice(const StepLaunch &a)
         using F0 = std::integral_constant<int, FORCE_II>;
         using F1 = std::integral_constant<int, FORCE_II_G>;
         using F2 = std::integral_constant<int, FORCE_GUO>;
-        auto with_forcing = [&](auto mc) {
-            if (a.forcing == FORCE_II_G) with_nt(std::true_type{}, mc, F1{});
-            else if (a.forcing == FORCE_GUO) with_nt(std::true_type{}, mc, F2{});
-            else with_nt(std::true_type{}, mc, F0{});
+        auto run = [&](auto oc) {
+            constexpr bool OP = decltype(oc)::value;
+            auto with_nt = [&](auto rowc, auto mc, auto fc) {
+                if (a.nt) go(rowc, std::true_type{}, mc, fc, oc);
+                else go(rowc, std::false_type{}, mc, fc, oc);
+            };
+            auto with_forcing = [&](auto mc) {
+                if (a.forcing == FORCE_GUO) {
+                    with_nt(std::true_type{}, mc, F2{});
+                } else if (a.forcing == FORCE_II_G) {
+                    if constexpr (!OP) with_nt(std::true_type{}, mc, F1{});
+                } else {
+                    with_nt(std::true_type{}, mc, F0{});
+                }
+            };
+            if (!a.row) {
+                // other models, forcings and boundaries need row workgroups
+                if constexpr (!OP) with_nt(std::false_type{}, P0{}, F0{});
+            } else if (a.model == MODEL_TRT_RLB) {
+                with_nt(std::true_type{}, P1{}, F0{});
+            } else if (a.model == MODEL_TRT) {
+                with_nt(std::true_type{}, P2{}, F0{});
+            } else if (a.model == MODEL_PTRT_EXACT) {
+                // the fifth-order modes exist on D3Q27 only; elsewhere it is P-TRT
+                if constexpr (L::Q == 27) with_forcing(P3{});
+                else with_forcing(P0{});
+            } else {
+                with_forcing(P0{});
+            }
         };
-        if (!a.row) {
-            with_nt(std::false_type{}, P0{}, F0{}); // other models / forcings need row workgroups
-        } else if (a.model == MODEL_TRT_RLB) {
-            with_nt(std::true_type{}, P1{}, F0{});
-        } else if (a.model == MODEL_TRT) {
-            with_nt(std::true_type{}, P2{}, F0{});
-        } else if (a.model == MODEL_PTRT_EXACT) {
-            // the fifth-order modes exist on D3Q27 only; elsewhere it is P-TRT
-            if constexpr (L::Q == 27) with_forcing(P3{});
-            else with_forcing(P0{});
+        if constexpr (L::Q == 9) {
+            if (a.open) run(std::true_type{});
+            else run(std::false_type{});
         } else {
-            with_forcing(P0{});
+            run(std::false_type{});
         }
         return PTRT_OK;
     });

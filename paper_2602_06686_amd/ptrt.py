@@ -62,6 +62,8 @@ _SIGS = {
     "ptrt_set_storage": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_model": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_forcing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_set_open_x": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+    "ptrt_momentum_exchange": (ctypes.c_int, [_vp, _dp]),
     "ptrt_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ptrt_init_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
     "ptrt_step": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -172,6 +174,16 @@ def ptrt_set_forcing(h, forcing):
     return _check(_lib.ptrt_set_forcing(h.ptr, forcing), h.ptr)
 
 
+def ptrt_set_open_x(h, u_in, rho_out):
+    return _check(_lib.ptrt_set_open_x(h.ptr, float(u_in), float(rho_out)), h.ptr)
+
+
+def ptrt_momentum_exchange(h):
+    F = np.zeros(3)
+    _check(_lib.ptrt_momentum_exchange(h.ptr, _ptr(F)), h.ptr)
+    return F
+
+
 def ptrt_set_stream(h, stream):
     return _check(_lib.ptrt_set_stream(h.ptr, _stream_handle(stream)), h.ptr)
 
@@ -255,7 +267,7 @@ class Lattice:
     """Convenience owner of one handle: create / init / step / read back."""
 
     def __init__(self, lattice, nx, ny, nz, tau_plus, Lambda, force=None, solid_mask=None,
-                 storage="f32", stream=None, model="ptrt", forcing="scheme2"):
+                 storage="f32", stream=None, model="ptrt", forcing="scheme2", open_x=None):
         self.h = ptrt_create(lattice, nx, ny, nz, tau_plus, Lambda, force, solid_mask)
         try:
             ptrt_set_storage(self.h, storage)
@@ -263,6 +275,8 @@ class Lattice:
                 ptrt_set_model(self.h, model)
             if forcing != "scheme2":
                 ptrt_set_forcing(self.h, forcing)
+            if open_x is not None:
+                ptrt_set_open_x(self.h, *open_x)
             if stream is not None:
                 ptrt_set_stream(self.h, stream)
         except Exception:
@@ -283,6 +297,9 @@ class Lattice:
 
     def populations(self):
         return ptrt_get_populations(self.h)
+
+    def momentum_exchange(self):
+        return ptrt_momentum_exchange(self.h)
 
     def set_populations(self, f):
         ptrt_set_populations(self.h, f)
