@@ -66,6 +66,8 @@ def _load():
                                            ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
                                            ctypes.c_int, ctypes.c_int]
         lib.ptrt_oracle_run_open.argtypes = lib.ptrt_oracle_run_ex.argtypes + [_dp]
+        lib.ptrt_oracle_apply_outlet.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, _u8p, _dp, ctypes.c_double]
         lib.ptrt_oracle_momentum_exchange.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
             ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp, _dp, _dp]
@@ -224,6 +226,17 @@ class Lattice:
     def set_populations(self, f_qzyx):
         f_qzyx = np.asarray(f_qzyx, dtype=np.float64).reshape((self.Q,) + self.shape)
         self.f = np.ascontiguousarray(f_qzyx.reshape(self.Q, self.N).T)
+        self._apply_outlet()
+
+    def _apply_outlet(self):
+        """With open x the outlet condition also holds for a state set from
+        outside (its entering populations are computed, not stored)."""
+        if self.open_x is None:
+            return
+        nz, ny, nx = self.shape
+        solid = _p(self.solid, _u8p) if self.solid is not None else None
+        assert _load().ptrt_oracle_apply_outlet(self.lat, nx, ny, nz, solid, _p(self.f),
+                                                float(self.open_x[1])) == 0
 
     def populations(self):
         return np.ascontiguousarray(self.f.T).reshape((self.Q,) + self.shape)
@@ -237,6 +250,7 @@ class Lattice:
             u3[: u.shape[0]] = u.reshape((u.shape[0],) + self.shape)
         feq = equilibrium(self.lat, rho.ravel(), u3.reshape(3, -1).T)
         self.f = np.ascontiguousarray(feq)
+        self._apply_outlet()
         self.t = 0
 
     # ---- dynamics ------------------------------------------------------

@@ -36,7 +36,8 @@
  *     f_3 = f_1 - (2/3) rho u_x, f_7 = f_5 + (f_2 - f_4)/2 - rho u_x / 6,
  *     f_6 = f_8 - (f_2 - f_4)/2 - rho u_x / 6, with
  *     u_x = (f_0 + f_2 + f_4 + 2 (f_1 + f_5 + f_8)) / rho_out - 1.
- *     y stays periodic.  Momentum exchange (Eq. Fx): on a halfway
+ *     The outlet condition holds at every time, so it is also applied to
+ *     the initial state.  y stays periodic.  Momentum exchange (Eq. Fx): on a halfway
  *     bounce-back wall the population re-entering the fluid equals the one
  *     that left, so F = sum over fluid-solid links of 2 e_i f*_i(x_f).
  *  R17 (Scheme I, Eq. source_guo).  As printed, the -u.F/c_s^2 part sits
@@ -697,6 +698,19 @@ int ptrt_oracle_run_ex(int id, int model, int forcing, int nx, int ny, int nz, d
 {
     return run_impl(id, model, forcing, nx, ny, nz, tau_plus, Lambda, tau_minus, g, solid, f,
                     nsteps, nthreads, NULL);
+}
+
+/* Apply the outlet condition of R18 to a state f [N][Q] (the outlet holds it
+ * at every time, the initial state included). */
+int ptrt_oracle_apply_outlet(int id, int nx, int ny, int nz, const uint8_t *solid, double *f,
+                             double rho_out)
+{
+    if (id != 0 || nz != 1 || !(rho_out > 0.0)) return -6;
+    for (int y = 0; y < ny; ++y) {
+        size_t m = node_index(nx - 1, y, 0, nx, ny);
+        if (!(solid && solid[m])) zou_he_outlet(f + m * 9, rho_out);
+    }
+    return 0;
 }
 
 /* The same with the open boundaries of R18 (D2Q9): open = {u_in, rho_out}. */
