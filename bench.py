@@ -9,8 +9,9 @@ form (512 uneven lattices, one graph-replayed launch per step, and the
 one-launch-per-lattice comparison), and the two D2Q9 single-lattice
 configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64),
 the collision-model comparison, D3Q27 (hybrid P-TRT, FP32 / FP16, and
-its comparison models) on the 256^3 vortex, and the forcing schemes
-(Scheme II with the cubic correction, Scheme I) against the default.
+its comparison models) on the 256^3 vortex, the forcing schemes (Scheme II
+with the cubic correction, Scheme I) against the default, and the square
+cylinder with open boundaries and the momentum-exchange force.
 
 ``roofline`` describes the dominant kernel (the D3Q19 FP32 step): the
 algorithmic bytes per launch (2 * 19 * 4 bytes per node) over the average
@@ -255,6 +256,41 @@ def form_forcing(P, torch, stream, steps, warmup):
     return out
 
 
+def form_cylinder(P, torch, stream, steps, warmup):
+    """Creeping flow past a square cylinder (Sec. 3.4): D2Q9, D = 21,
+    L = 50 D (1050^2 nodes), moving-wall inlet, Zou-He outlet, periodic y,
+    Re = 0.1, T = 0.1, Lambda = 3/16; fused step in FP64 and FP32 and the
+    momentum-exchange reduction, from the uniform stream."""
+    import numpy as np
+    D, K, Re, T = 21, 50, 0.1, 0.1
+    n = D * K
+    uc = (T * Re) ** 0.5 / 3 ** 0.5
+    tp = 3 * uc * D / Re + 0.5
+    mask = np.zeros((1, n, n), dtype=np.uint8)
+    c0 = n // 2 - D // 2
+    mask[0, c0:c0 + D, c0:c0 + D] = 1
+    u = np.zeros((3, 1, n, n))
+    u[0] = uc
+    out = {"workload": "D2Q9 P-TRT square cylinder 1050^2 (D=21, L=50D, Re=0.1, Ma=0.1, "
+                       "velocity inlet + Zou-He outlet, Lambda=3/16)"}
+    for storage in ("f64", "f32"):
+        with P.Lattice(0, n, n, 1, tp, 3 / 16, solid_mask=mask, storage=storage, stream=stream,
+                       open_x=(uc, 1.0)) as L:
+            L.init_equilibrium(None, u)
+            ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+            t0 = time.perf_counter()
+            for _ in range(10):
+                F = L.momentum_exchange()
+            mx = (time.perf_counter() - t0) / 10 * 1e3
+            bpn = L.bytes_per_node
+        mps = ms / steps
+        out[storage] = {"ms_per_step": mps, "mlups": n * n / (mps * 1e-3) / 1e6,
+                        "achieved_gbs": bpn * n * n / (mps * 1e-3) / 1e9,
+                        "momentum_exchange_ms_host": mx,
+                        "cd_after_timed_steps": 2 * F[0] / (uc * uc * D)}
+    return out
+
+
 def cpu_baseline(n=256, steps=12):
     """The FP64 C oracle, as it is, on `steps` steps of the headline lattice."""
     import lbm_inputs as I
@@ -302,7 +338,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default=None,
                     help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, models, "
-                         "d3q27, forcing, tgv64")
+                         "d3q27, forcing, cylinder, tgv64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -356,6 +392,10 @@ def main():
         log("forcing schemes")
         forms["forcing_fp32"] = form_forcing(P, torch, stream, max(20, K // 2), max(2, W // 2))
         log(json.dumps(forms["forcing_fp32"]))
+    if only in (None, "cylinder"):
+        log("square cylinder")
+        forms["cylinder_d2q9"] = form_cylinder(P, torch, stream, K, W)
+        log(json.dumps(forms["cylinder_d2q9"]))
     if only in (None, "tgv64"):
         log("D2Q9 FP64 64^2")
         forms["d2q9_64_f64"] = form_tgv64(P, torch, stream, 1000, 50)
