@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "codec.hpp"
 #include "collide.hpp"
 #include "lattice.hpp"
@@ -44,16 +46,24 @@ struct Geom {
 // is at row_base(g, q, row) + x.  Kept apart from x so that, when the row is
 // uniform across a wave, the base is computed on the scalar unit and the
 // loads use a scalar base with a 32-bit per-lane offset.
+// The part inside a tile (direction chunk and row within the tile) is
+// computed in 32 bits: a tile holds Q * nx << lr < 2^32 elements.
 __device__ __forceinline__ long long row_base(const Geom &g, int q, unsigned row)
 {
-    return (long long)(row >> g.lr) * g.tile + (long long)q * g.plane +
-           (long long)((row & ((1u << g.lr) - 1u)) * (unsigned)g.nx);
+    const unsigned in_tile =
+        (unsigned)q * (unsigned)g.plane + (row & ((1u << g.lr) - 1u)) * (unsigned)g.nx;
+    return (long long)(row >> g.lr) * g.tile + (long long)in_tile;
 }
 
+// The x part is added as a 32-bit byte offset, so that with a row-uniform
+// base the access can use a scalar 64-bit base plus a 32-bit lane offset
+// (no 64-bit address arithmetic per lane).
 template <class S>
 __device__ __forceinline__ S *at(S *base, const Geom &g, int q, unsigned row, int x)
 {
-    return (base + row_base(g, q, row)) + (unsigned)x;
+    using B = typename std::conditional<std::is_const<S>::value, const char, char>::type;
+    return reinterpret_cast<S *>(reinterpret_cast<B *>(base + row_base(g, q, row)) +
+                                 (unsigned)x * (unsigned)sizeof(S));
 }
 
 // Source of population I pulled into (x, y, z): x coordinate and row of
