@@ -141,18 +141,23 @@ inline std::vector<uint8_t> near_solid_rows(const uint8_t *mask, int nx, int ny,
     return near;
 }
 
-// Tiled layout of a lattice (see kernels.hpp): rows per tile chosen so one
-// direction chunk of a tile is about 8 KB.  Returns the element count of a
-// population buffer and fills g.
+// Tiled layout of a lattice (see kernels.hpp): rows padded to a pitch of a
+// whole number of 128-byte lines (a wave's row segment then starts on a
+// line boundary, so no line is written partly by two waves), rows per tile
+// chosen so one direction chunk of a tile is about 8 KB.  Returns the
+// element count of a population buffer and fills g.
 inline long long make_layout(int Q, int nx, int ny, int nz, size_t elem, Geom &g)
 {
+    const int line = (int)(128 / elem);
+    const int pitch = (nx + line - 1) / line * line;
     int lr = 0;
-    while (((long long)nx << (lr + 1)) * (long long)elem <= 8192) ++lr;
+    while (((long long)pitch << (lr + 1)) * (long long)elem <= 8192) ++lr;
     g.nx = nx;
     g.ny = ny;
     g.nz = nz;
+    g.pitch = pitch;
     g.lr = lr;
-    g.plane = (long long)nx << lr;
+    g.plane = (long long)pitch << lr;
     g.tile = (long long)Q * g.plane;
     const long long rows = (long long)ny * nz;
     const long long ntiles = (rows + (1LL << lr) - 1) >> lr;

@@ -2,12 +2,13 @@
 // state scatter used by initialisation and restore, the gather used by
 // moments / populations / diagnostics, and the FP64 reductions.
 //
-// Layout (one lattice): rows of nx nodes (row = z * ny + y, x fastest) are
-// grouped into tiles of R = 2^lr rows; a tile stores direction 0 of its R
-// rows, then direction 1, ..., then direction Q-1, each as a contiguous
-// chunk of plane = R * nx shifted populations h_i = f_i - w_i.  Element
+// Layout (one lattice): rows of nx nodes (row = z * ny + y, x fastest),
+// stored with a pitch of nx rounded up to whole 128-byte lines, are grouped
+// into tiles of R = 2^lr rows; a tile stores direction 0 of its R rows, then
+// direction 1, ..., then direction Q-1, each as a contiguous chunk of
+// plane = R * pitch shifted populations h_i = f_i - w_i.  Element
 // (i, row, x) sits at  (row >> lr) * Q * plane + i * plane
-// + (row & (R-1)) * nx + x.  With R large enough to hold every row this is
+// + (row & (R-1)) * pitch + x.  With R large enough to hold every row this is
 // the plain direction-major (SoA) layout; with chunks of a few KB the Q
 // streams of a step stay inside one tile, which keeps the HBM pages that a
 // wave touches close together.
@@ -33,8 +34,9 @@ namespace ptrt {
 
 struct Geom {
     int nx, ny, nz;
+    int pitch;       // elements per stored row (nx rounded up to whole 128-byte lines)
     int lr;          // log2 of rows per tile
-    long long plane; // elements of one direction inside a tile: nx << lr
+    long long plane; // elements of one direction inside a tile: pitch << lr
     long long tile;  // elements of a tile: Q * plane
     // Open boundaries in x (D2Q9, kernels with OPEN = true only): inlet wall
     // at x = -1/2 moving with (uin, 0), pressure outlet rho = 1 + drhoout at
@@ -51,7 +53,7 @@ struct Geom {
 __device__ __forceinline__ long long row_base(const Geom &g, int q, unsigned row)
 {
     const unsigned in_tile =
-        (unsigned)q * (unsigned)g.plane + (row & ((1u << g.lr) - 1u)) * (unsigned)g.nx;
+        (unsigned)q * (unsigned)g.plane + (row & ((1u << g.lr) - 1u)) * (unsigned)g.pitch;
     return (long long)(row >> g.lr) * g.tile + (long long)in_tile;
 }
 
