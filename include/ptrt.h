@@ -162,6 +162,24 @@ int ptrt_set_model(ptrt_ctx *ctx, int model);
  * fails.  Default PTRT_FORCING_SCHEME2. */
 int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
 
+/* Steps per pass over the populations (1 or 2; default 2).  With 2, pairs
+ * of steps run as one kernel that keeps the first step's results in LDS
+ * (temporal blocking) where the configuration allows it: D3Q19 in FP32,
+ * no solid nodes, periodic boundaries, PTRT_MODEL_PTRT,
+ * PTRT_FORCING_SCHEME2, nx a multiple of 64 and ny a multiple of 4; every
+ * other case, and an odd last step, runs one step per pass.  Results are
+ * bit-identical either way.  Allowed at any time (waits for the handle's
+ * stream). */
+int ptrt_set_steps_per_pass(ptrt_ctx *ctx, int steps);
+
+/* The most recent kernel pass enqueued by ptrt_step: *steps = the steps it
+ * covers (1 or 2; 0 before any step) and *bytes = its algorithmic HBM
+ * traffic in bytes (one step: 2 Q s per node, plus one mask byte per node
+ * with solids; two steps: Q s per node read by the first step over each
+ * workgroup's column and halo, Q s per node written by the second).  For
+ * bandwidth accounting; no synchronisation. */
+int ptrt_last_pass(const ptrt_ctx *ctx, int *steps, double *bytes);
+
 /* Open boundaries in x instead of periodic x (Sec. 3.4, creeping flow past
  * a square cylinder; D2Q9 only).  Inlet: a halfway bounce-back wall at
  * x = -1/2 moving with velocity (u_in, 0) and density rho_0 = 1; a

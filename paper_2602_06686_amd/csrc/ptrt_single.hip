@@ -51,6 +51,9 @@ struct ptrt_ctx {
     int forcing = FORCE_II;
     void *d_phi = nullptr; // Phi field of the cubic correction (compute type)
     bool open = false;     // D2Q9 velocity inlet / pressure outlet in x
+    int steps_per_pass = 2; // up to two fused steps per pass where allowed
+    int last_pass_steps = 0;      // steps covered by the most recent pass
+    double last_pass_bytes = 0.0; // its algorithmic HBM bytes
     double *d_force_parts = nullptr, *d_force = nullptr; // momentum exchange
     // small lattices: steps replayed from captured graphs of GRAPH_STEPS launches
     bool use_graph = false;
@@ -263,8 +266,39 @@ int download_state(ptrt_ctx *c, double *rho, double *u, double *f)
     return rc;
 }
 
+StepLaunch step_args(const ptrt_ctx *c, hipStream_t s);
+
 // Enqueue one fused step on stream s (buffer cur -> cur ^ 1).
 void launch_step(ptrt_ctx *c, hipStream_t s)
+{
+    const StepLaunch a = step_args(c, s);
+    c->last_pass_steps = 1;
+    c->last_pass_bytes = (double)c->N * (2.0 * c->Q * storage_bytes(c->storage) + (c->has_mask ? 1.0 : 0.0));
+    if (c->lattice == PTRT_D2Q9) launch_step_d2q9(a);
+    else if (c->lattice == PTRT_D3Q19) launch_step_d3q19(a);
+    else launch_step_d3q27(a);
+    c->cur ^= 1;
+}
+
+// Enqueue n steps: pairs in one pass where the configuration allows it.
+void launch_steps(ptrt_ctx *c, hipStream_t s, int n)
+{
+    while (n >= 2 && c->steps_per_pass == 2) {
+        const StepLaunch a = step_args(c, s);
+        bool two = false;
+        double bytes = 0.0;
+        if (c->lattice == PTRT_D3Q19) two = launch_step2_d3q19(a, &bytes);
+        else if (c->lattice == PTRT_D3Q27) two = launch_step2_d3q27(a, &bytes);
+        if (!two) break;
+        c->cur ^= 1;
+        c->last_pass_steps = 2;
+        c->last_pass_bytes = bytes;
+        n -= 2;
+    }
+    for (; n > 0; --n) launch_step(c, s);
+}
+
+StepLaunch step_args(const ptrt_ctx *c, hipStream_t s)
 {
     StepLaunch a;
     a.src = c->buf[c->cur];
@@ -285,10 +319,7 @@ void launch_step(ptrt_ctx *c, hipStream_t s)
     a.phi = c->d_phi;
     a.open = c->open;
     a.stream = s;
-    if (c->lattice == PTRT_D2Q9) launch_step_d2q9(a);
-    else if (c->lattice == PTRT_D3Q19) launch_step_d3q19(a);
-    else launch_step_d3q27(a);
-    c->cur ^= 1;
+    return a;
 }
 
 // Bytes of the Phi field: D components per node in the compute type.
@@ -330,7 +361,7 @@ int capture_graph(ptrt_ctx *c, int parity)
     c->cur = parity;
     hipGraph_t gr = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < GRAPH_STEPS; ++k) launch_step(c, c->capture_stream);
+    launch_steps(c, c->capture_stream, GRAPH_STEPS);
     hipError_t e = hipStreamEndCapture(c->capture_stream, &gr);
     c->cur = saved;
     if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
@@ -465,6 +496,25 @@ int ptrt_momentum_exchange(ptrt_ctx *c, double force_out[3])
     return PTRT_OK;
 }
 
+int ptrt_last_pass(const ptrt_ctx *c, int *steps, double *bytes)
+{
+    if (!c || !steps || !bytes) return PTRT_EINVAL;
+    *steps = c->last_pass_steps;
+    *bytes = c->last_pass_bytes;
+    return PTRT_OK;
+}
+
+int ptrt_set_steps_per_pass(ptrt_ctx *c, int steps)
+{
+    if (!c) return PTRT_EINVAL;
+    if (steps != 1 && steps != 2) return fail(c, PTRT_EINVAL, "steps per pass must be 1 or 2");
+    if (c->allocated && hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
+    c->steps_per_pass = steps;
+    drop_graphs(c);
+    return PTRT_OK;
+}
+
 int ptrt_set_forcing(ptrt_ctx *c, int forcing)
 {
     if (!c) return PTRT_EINVAL;
@@ -532,7 +582,7 @@ int ptrt_step(ptrt_ctx *c, int n)
             HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
             n -= GRAPH_STEPS;
         }
-    for (; n > 0; --n) launch_step(c, c->stream);
+    launch_steps(c, c->stream, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return PTRT_OK;

@@ -5,4 +5,9 @@ namespace ptrt {
 
 void launch_step_d3q27(const StepLaunch &a) { launch_step_lattice<D3Q27>(a); }
 
+bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes)
+{
+    return launch_step2_lattice<D3Q27>(a, pass_bytes);
+}
+
 } // namespace ptrt

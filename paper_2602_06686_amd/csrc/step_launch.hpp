@@ -5,6 +5,7 @@
 #pragma once
 
 #include "host_common.hpp"
+#include "step2.hpp"
 
 namespace ptrt {
 
@@ -28,6 +29,54 @@ struct StepLaunch {
 void launch_step_d2q9(const StepLaunch &a);
 void launch_step_d3q19(const StepLaunch &a);
 void launch_step_d3q27(const StepLaunch &a);
+
+// Two steps in one pass (step2.hpp) when the configuration allows it:
+// returns false (nothing launched) otherwise.
+// *pass_bytes: the algorithmic HBM bytes of the pass (the first step's reads
+// over the column and its halo, the second step's writes).
+bool launch_step2_d3q19(const StepLaunch &a, double *pass_bytes);
+bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes);
+
+template <class L>
+bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
+{
+    if constexpr (L::D != 3) {
+        return false;
+    } else {
+        if (a.has_mask || a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II)
+            return false;
+        bool launched = false;
+        dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
+            using S = typename decltype(st)::type;
+            using C = typename Codec<S>::compute;
+            using SH = Step2Shape<L, S>;
+            if constexpr (SH::available) {
+                if (a.g.nx % SH::BX != 0 || a.g.ny % SH::BY != 0) return PTRT_OK;
+                // z chunks: enough workgroups to fill the chip several times
+                const long long cols = (long long)(a.g.nx / SH::BX) * (a.g.ny / SH::BY);
+                int zc = a.g.nz;
+                while (zc > 8 && cols * ((a.g.nz + zc - 1) / zc) < 1024) zc = (zc + 1) / 2;
+                const dim3 grid(a.g.nx / SH::BX, a.g.ny / SH::BY, (a.g.nz + zc - 1) / zc);
+                const dim3 block(64 * SH::WAVES, 1, 1);
+                if (pass_bytes) {
+                    const double a_nodes = (double)cols * SH::AP * (a.g.nz + 2.0 * grid.z);
+                    const double b_nodes = (double)a.g.nx * a.g.ny * a.g.nz;
+                    *pass_bytes = (a_nodes + b_nodes) * L::Q * sizeof(S);
+                }
+                const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
+                if (a.nt)
+                    hipLaunchKernelGGL((k_step2<L, S, true>), grid, block, 0, a.stream,
+                                       (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                else
+                    hipLaunchKernelGGL((k_step2<L, S, false>), grid, block, 0, a.stream,
+                                       (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                launched = true;
+            }
+            return PTRT_OK;
+        });
+        return launched;
+    }
+}
 
 // Model and forcing combinations that have kernels: the comparison models
 // (TRT-RLB, TRT) use Scheme II without G_i; the forcing variants and the

@@ -63,6 +63,8 @@ _SIGS = {
     "ptrt_set_model": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_forcing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_set_open_x": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+    "ptrt_set_steps_per_pass": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_last_pass": (ctypes.c_int, [_vp, _ip, _dp]),
     "ptrt_momentum_exchange": (ctypes.c_int, [_vp, _dp]),
     "ptrt_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ptrt_init_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
@@ -174,6 +176,18 @@ def ptrt_set_forcing(h, forcing):
     return _check(_lib.ptrt_set_forcing(h.ptr, forcing), h.ptr)
 
 
+def ptrt_set_steps_per_pass(h, steps):
+    return _check(_lib.ptrt_set_steps_per_pass(h.ptr, int(steps)), h.ptr)
+
+
+def ptrt_last_pass(h):
+    """(steps covered, algorithmic HBM bytes) of the most recent kernel pass."""
+    steps = ctypes.c_int()
+    nbytes = ctypes.c_double()
+    _check(_lib.ptrt_last_pass(h.ptr, ctypes.byref(steps), ctypes.byref(nbytes)), h.ptr)
+    return steps.value, nbytes.value
+
+
 def ptrt_set_open_x(h, u_in, rho_out):
     return _check(_lib.ptrt_set_open_x(h.ptr, float(u_in), float(rho_out)), h.ptr)
 
@@ -267,7 +281,8 @@ class Lattice:
     """Convenience owner of one handle: create / init / step / read back."""
 
     def __init__(self, lattice, nx, ny, nz, tau_plus, Lambda, force=None, solid_mask=None,
-                 storage="f32", stream=None, model="ptrt", forcing="scheme2", open_x=None):
+                 storage="f32", stream=None, model="ptrt", forcing="scheme2", open_x=None,
+                 steps_per_pass=2):
         self.h = ptrt_create(lattice, nx, ny, nz, tau_plus, Lambda, force, solid_mask)
         try:
             ptrt_set_storage(self.h, storage)
@@ -277,6 +292,8 @@ class Lattice:
                 ptrt_set_forcing(self.h, forcing)
             if open_x is not None:
                 ptrt_set_open_x(self.h, *open_x)
+            if steps_per_pass != 2:
+                ptrt_set_steps_per_pass(self.h, steps_per_pass)
             if stream is not None:
                 ptrt_set_stream(self.h, stream)
         except Exception:
@@ -300,6 +317,9 @@ class Lattice:
 
     def momentum_exchange(self):
         return ptrt_momentum_exchange(self.h)
+
+    def last_pass(self):
+        return ptrt_last_pass(self.h)
 
     def set_populations(self, f):
         ptrt_set_populations(self.h, f)
