@@ -89,8 +89,10 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     constexpr int BX = SH::BX, BY = SH::BY, AX = SH::AX, AY = SH::AY, AP = SH::AP;
     __shared__ S lds[K::planes * AP];
 
-    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY;
-    const int zs = blockIdx.z * zc;
+    int bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int x0 = bx * BX, y0 = by * BY;
+    const int zs = bz * zc;
     const int ze = min(zs + zc, g.nz);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
