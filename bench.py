@@ -15,10 +15,11 @@ cylinder with open boundaries and the momentum-exchange force.
 
 ``roofline`` describes the dominant kernel of the headline: the pass that
 runs two D3Q19 FP32 steps per launch (first step over each workgroup's
-column and halo, kept in LDS; second step written back), its algorithmic
-HBM bytes per launch (reported by the library) over the average launch
-time, against the 8 TB/s HBM peak; beside it the MLUPS as a fraction of the
-one-step roofline (8 TB/s over 2 * 19 * 4 bytes per node and step).  ``traffic`` is read from the
+column and halo, kept in LDS; second step written back).  Its algorithmic
+HBM bytes per launch (reported by the library: the state read once and
+written once, 2 * 19 * 4 bytes per node for two steps) over the average
+launch time, against the 8 TB/s HBM peak; beside it the MLUPS as a fraction
+of the one-step roofline (8 TB/s over 2 * 19 * 4 bytes per node and step).  ``traffic`` is read from the
 committed rocprofv3 counter summary when it was taken on the current kernel
 sources, else null.  ``cpu_baseline`` times the FP64 C oracle on twelve steps
 of the same 256^3 lattice on the host cores.
@@ -182,7 +183,8 @@ def form_batch(P, torch, stream, steps, warmup):
 def form_models(P, torch, stream, steps, warmup):
     """P-TRT against TRT-RLB (Hermite projection) and standard TRT kernels in
     the same harness: the paper's efficiency comparison (Table efficiency)
-    on this GPU, for the D2Q9 shear layer and the D3Q19 vortex (FP32)."""
+    on this GPU, for the D2Q9 shear layer and the D3Q19 vortex (FP32), each
+    model with one step per pass."""
     import lbm_inputs as I
     out = {}
     n2, U0 = 2048, 0.05
@@ -196,7 +198,9 @@ def form_models(P, torch, stream, steps, warmup):
         rho, u = init()
         res = {}
         for model in ("ptrt", "trt-rlb", "trt"):
-            with P.Lattice(lat, nx, ny, nz, tp, 0.25, storage="f32", stream=stream, model=model) as L:
+            # one step per pass for every model: a kernel-to-kernel comparison
+            with P.Lattice(lat, nx, ny, nz, tp, 0.25, storage="f32", stream=stream, model=model,
+                           steps_per_pass=1) as L:
                 L.init_equilibrium(rho, u)
                 ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
                 res[model] = {"ms_per_step": ms / steps, "mlups": nx * ny * nz * steps / (ms * 1e-3) / 1e6}
@@ -255,7 +259,7 @@ def form_forcing(P, torch, stream, steps, warmup):
         res = {}
         for forcing in ("scheme2", "scheme2+g", "guo"):
             with P.Lattice(lat, nx, ny, nz, tp, 0.25, force=[1e-6, 0, 0], storage="f32",
-                           stream=stream, forcing=forcing) as L:
+                           stream=stream, forcing=forcing, steps_per_pass=1) as L:
                 L.init_equilibrium(rho, u)
                 ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
             mps = ms / steps

@@ -175,9 +175,9 @@ int ptrt_set_steps_per_pass(ptrt_ctx *ctx, int steps);
 /* The most recent kernel pass enqueued by ptrt_step: *steps = the steps it
  * covers (1 or 2; 0 before any step) and *bytes = its algorithmic HBM
  * traffic in bytes (one step: 2 Q s per node, plus one mask byte per node
- * with solids; two steps: Q s per node read by the first step over each
- * workgroup's column and halo, Q s per node written by the second).  For
- * bandwidth accounting; no synchronisation. */
+ * with solids; two steps: also 2 Q s per node, the state read once by the
+ * first step and written once by the second).  For bandwidth accounting;
+ * no synchronisation. */
 int ptrt_last_pass(const ptrt_ctx *ctx, int *steps, double *bytes);
 
 /* Open boundaries in x instead of periodic x (Sec. 3.4, creeping flow past
