@@ -287,7 +287,8 @@ void launch_steps(ptrt_ctx *c, hipStream_t s, int n)
         const StepLaunch a = step_args(c, s);
         bool two = false;
         double bytes = 0.0;
-        if (c->lattice == PTRT_D3Q19) two = launch_step2_d3q19(a, &bytes);
+        if (c->lattice == PTRT_D2Q9) two = launch_step2_d2q9(a, &bytes);
+        else if (c->lattice == PTRT_D3Q19) two = launch_step2_d3q19(a, &bytes);
         else if (c->lattice == PTRT_D3Q27) two = launch_step2_d3q27(a, &bytes);
         if (!two) break;
         c->cur ^= 1;

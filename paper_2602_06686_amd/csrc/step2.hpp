@@ -23,10 +23,14 @@
 
 namespace ptrt {
 
-template <class L>
+// Direction classes along the marching axis (z in 3D, y in 2D).
+template <class L, int AXIS = L::D - 1>
 struct Step2Classes {
     // class of a direction: 0 (e_z = -1), 1 (e_z = 0), 2 (e_z = +1)
-    __host__ __device__ static constexpr int cls(int i) { return L::ez(i) + 1; }
+    __host__ __device__ static constexpr int cls(int i)
+    {
+        return (AXIS == 2 ? L::ez(i) : L::ey(i)) + 1;
+    }
     __host__ __device__ static constexpr int count(int c)
     {
         int n = 0;
@@ -51,7 +55,7 @@ struct Step2Classes {
     static constexpr int planes = count(0) * slots(0) + count(1) * slots(1) + count(2) * slots(2);
 };
 
-// Workgroup rows for the storage type (LDS stays within 64 KB).
+// Workgroup rows for the storage type.
 template <class L, class S>
 struct Step2Shape {
     static constexpr int BX = 64;
@@ -60,12 +64,24 @@ struct Step2Shape {
     // the halo's extra collisions outweigh the halved traffic
     static constexpr int BY = (sizeof(S) == 4 && L::Q == 19) ? 4 : 0;
     static constexpr int AX = BX + 2, AY = BY + 2, AP = AX * AY;
-    // one wave per interior row; the A tasks (AY rows and the halo columns)
-    // are shared out over them
+    // one wave per interior row; the AY + 1 first-step tasks (AY rows and
+    // the halo columns) are shared out over them, at most two per wave
     static constexpr int WAVES = BY;
-    static constexpr size_t lds_bytes = (size_t)Step2Classes<L>::planes * AP * sizeof(S);
-    static constexpr bool available = BY > 0 && sizeof(S) <= 4 && lds_bytes <= 163840;
+    using K = Step2Classes<L>;
+    static constexpr size_t lds_bytes = (size_t)K::planes * AP * sizeof(S);
+    static constexpr bool available =
+        BY >= 3 && sizeof(S) <= 4 && lds_bytes <= 163840 && AY + 1 <= 2 * WAVES;
 };
+
+// Workgroup barrier that orders the LDS accesses only: the global loads in
+// flight (the next plane's first-step pulls) stay in flight across it,
+// where __syncthreads() would wait for them.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // P-TRT collision of the lattice (the hybrid of Eq. PTRT_D3Q27 on D3Q27).
 template <class L, class C>
@@ -84,8 +100,8 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         Coef<L, typename Codec<S>::compute> r, int zc)
 {
     using C = typename Codec<S>::compute;
-    using K = Step2Classes<L>;
     using SH = Step2Shape<L, S>;
+    using K = typename SH::K;
     constexpr int BX = SH::BX, BY = SH::BY, AX = SH::AX, AY = SH::AY, AP = SH::AP;
     __shared__ S lds[K::planes * AP];
 
@@ -97,7 +113,6 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
     auto wrapc = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
-    auto ld = [](const S *p) { return Codec<S>::load(p); };
 
     // LDS element of direction i, slot s, A node a
     auto lds_at = [](int i_cls, int i_idx, int slot, int a) {
@@ -106,7 +121,8 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
 
     // A nodes of a task: rows 0 .. AY-1 at ax = 1 .. 64 (one wave per row,
     // the row uniform across the wave), then task AY: the two halo columns
-    // ax = 0 and ax = AX-1 of every row (2 AY lanes of one wave)
+    // ax = 0 and ax = AX-1 of every row (2 AY lanes of one wave; the other
+    // lanes load and compute the last node again and keep nothing)
     auto a_node = [&](int task, int &ax, int &ay) -> bool {
         if (task < AY) {
             ax = lane + 1;
@@ -114,22 +130,23 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
             return true;
         }
         ax = lane < AY ? 0 : AX - 1;
-        ay = lane < AY ? lane : lane - AY;
+        ay = lane < AY ? lane : min(lane - AY, AY - 1);
         return lane < 2 * AY;
     };
     // first step, part 1: pull the stored values of A node `task` of plane k
+    // (every lane loads, so that no load sits in a branch)
     auto load_a = [&](int task, int k, S (&raw)[L::Q]) {
         int ax, ay;
-        if (!a_node(task, ax, ay)) return;
+        a_node(task, ax, ay);
         const int gx = wrapc(x0 - 1 + ax, g.nx);
         const int gy = wrapc(y0 - 1 + ay, g.ny);
         const int gz = wrapc(k, g.nz);
         pull<L, S, false>(src, nullptr, g, gx, gy, gz, raw, [](const S *p) { return *p; });
     };
-    // part 2: collide and keep the result in the class slots of iteration it
+    // part 2: collide and keep the result in the class slots of plane `it`
     auto finish_a = [&](int task, int it, const S (&raw)[L::Q]) {
         int ax, ay;
-        if (!a_node(task, ax, ay)) return;
+        const bool valid = a_node(task, ax, ay);
         C h[L::Q];
         static_for<L::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
@@ -137,32 +154,47 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         });
         C rho, ux, uy, uz;
         collide_ptrt<L, C>(h, r, rho, ux, uy, uz);
+        if (!valid) return;
         const int a = ay * AX + ax;
         static_for<L::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int c = K::cls(i);
-            const int slot = it % K::slots(c);
-            Codec<S>::template store<false>(&lds[lds_at(c, K::index(i), slot, a)], h[i]);
+            Codec<S>::template store<false>(&lds[lds_at(c, K::index(i), it % K::slots(c), a)],
+                                            h[i]);
         });
     };
 
-    // each wave owns A tasks w and w + BY (the second when <= AY); the loads
-    // of the next plane are issued before the second step of the current
-    // one, so that their latency overlaps it
+    // each wave owns A tasks w and w + BY (the second when <= AY); the
+    // optional task's loads go first, so that the wait for the other task's
+    // loads never has to count them
     const int t0 = w, t1 = w + BY;
     const bool has1 = t1 <= AY;
     S raw0[L::Q], raw1[L::Q];
-    load_a(t0, zs - 1, raw0);
-    if (has1) load_a(t1, zs - 1, raw1);
-    for (int k = zs - 1, it = 0; k <= ze; ++k, ++it) {
-        finish_a(t0, it, raw0);
+    auto load_both = [&](int k) {
+        if (has1) load_a(t1, k, raw1);
+        load_a(t0, k, raw0);
+    };
+    auto finish_both = [&](int it) {
         if (has1) finish_a(t1, it, raw1);
-        if (k < ze) {
-            load_a(t0, k + 1, raw0);
-            if (has1) load_a(t1, k + 1, raw1);
-        }
-        __syncthreads();
-        if (k >= zs + 1) {
+        finish_a(t0, it, raw0);
+    };
+    // first-step planes zs - 1, zs and zs + 1 (ze >= zs + 1), then for
+    // k = zs + 1 ... ze the second step of plane k - 1 followed by the first
+    // step of plane k + 1 (past the chunk the last plane is loaded again,
+    // so that the loop has no load or store under a branch).  Measured: the
+    // compiler's placement of the next plane's loads (after the second
+    // step, in the same block as their collisions) beats forcing them ahead
+    // of the second step.
+    load_both(zs - 1);
+    finish_both(0);
+    load_both(zs);
+    finish_both(1);
+    load_both(zs + 1);
+    finish_both(2);
+    load_both(min(zs + 2, ze));
+    for (int k = zs + 1, it = 2;; ++k, ++it) {
+        lds_barrier();
+        {
             // B: second step at interior node (x0 + lane, y0 + w, k - 1)
             const int ax = lane + 1, ay = w + 1;
             C h[L::Q];
@@ -170,8 +202,7 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
                 constexpr int i = decltype(ic)::value;
                 constexpr int c = K::cls(i);
                 // plane of the source: k (c = 0), k - 1 (c = 1), k - 2 (c = 2)
-                const int src_it = it - c;
-                const int slot = src_it % K::slots(c);
+                const int slot = (it - c) % K::slots(c);
                 const int a = (ay - L::ey(i)) * AX + (ax - L::ex(i));
                 h[i] = Codec<S>::load(&lds[lds_at(c, K::index(i), slot, a)]);
             });
@@ -184,8 +215,143 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
                 Codec<S>::template store<NT>(at(dst, g, i, row, x0 + lane), h[i]);
             });
         }
-        __syncthreads();
+        lds_barrier();
+        if (k == ze) break;
+        finish_both(it + 1);
+        load_both(min(k + 2, ze));
     }
+}
+
+} // namespace ptrt
+
+namespace ptrt {
+
+// Two fused steps per pass for D2Q9 without solids (the 2D counterpart of
+// k_step2): a workgroup is one wave that owns a strip of 62 columns and a
+// chunk of rows and marches up through its rows.  For row k the wave
+// computes the first step (A) on 64 nodes, columns x0 - 1 ... x0 + 62 (the
+// strip plus a one-column halo on each side), pulling from HBM, and keeps
+// the results in LDS in the storage type; lanes 1 ... 62 then compute the
+// second step (B) for row k - 1 from LDS and store it; the loads of rows
+// k + 1 and k + 2 are in flight meanwhile.  Population i of a B
+// node comes from the A node (x, y) - e_i: row k when e_iy = -1, k - 1 when
+// e_iy = 0, k - 2 when e_iy = +1 (1 + 2 + 3 slots of three directions,
+// 18 rows of 64 values).  Bit-identical to two one-step launches.
+template <class S>
+struct Step2Shape2D {
+    static constexpr int W = 64;         // A nodes per row (one wave)
+    static constexpr int BX = W - 2;     // interior columns per strip
+    static constexpr size_t lds_bytes = (size_t)Step2Classes<D2Q9>::planes * W * sizeof(S);
+};
+
+// Order of the LDS accesses of one wave (its lanes exchange values only
+// with each other).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class S, bool NT, int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
+           Coef<D2Q9, typename Codec<S>::compute> r, int yc, int strips, int tasks)
+{
+    using L = D2Q9;
+    using C = typename Codec<S>::compute;
+    using K = Step2Classes<D2Q9>;
+    constexpr int W = Step2Shape2D<S>::W, BX = Step2Shape2D<S>::BX;
+    __shared__ S lds_all[NW * K::planes * W];
+
+    // the NW waves of a workgroup run independent tasks (strip, chunk),
+    // neighbouring strips of one chunk
+    int wg, unused_y, unused_z;
+    xcd_block(wg, unused_y, unused_z);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int task = wg * NW + w;
+    if (task >= tasks) return;
+    S *lds = lds_all + w * (K::planes * W);
+    const int bx = task % strips, by = task / strips;
+    const int x0 = bx * BX;
+    const int ys = by * yc;
+    const int ye = min(ys + yc, g.ny);
+    const int lane = (int)(threadIdx.x & 63);
+    auto wrapc = [](int v, int n) {
+        v %= n;
+        return v < 0 ? v + n : v;
+    };
+    const int ax = wrapc(x0 - 1 + lane, g.nx); // this lane's A column
+    auto lds_at = [](int c, int idx, int slot, int a) {
+        return (K::region(c) + slot * K::count(c) + idx) * W + a;
+    };
+    auto load_a = [&](int k, S (&raw)[L::Q]) {
+        pull<L, S, false>(src, nullptr, g, ax, wrapc(k, g.ny), 0, raw, [](const S *p) { return *p; });
+    };
+    auto finish_a = [&](int it, const S (&raw)[L::Q]) {
+        C h[L::Q];
+        static_for<L::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            h[i] = Codec<S>::load(&raw[i]);
+        });
+        C rho, ux, uy, uz;
+        collide<L, C, true>(h, r, rho, ux, uy, uz);
+        static_for<L::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int c = K::cls(i);
+            Codec<S>::template store<false>(&lds[lds_at(c, K::index(i), it % K::slots(c), lane)], h[i]);
+        });
+    };
+
+    // B lanes: 1 ... BX, inside the lattice (the last strip may be partial)
+    const int bxg = x0 - 1 + lane;
+    const bool b_lane = lane >= 1 && lane <= BX && bxg < g.nx;
+    // one row of the march: finish A of row k from raw, refill raw with the
+    // loads of row k + 2 (two rows in flight; past the chunk the last row
+    // is loaded again), B of row k - 1.  Every wave issues the same loads
+    // and stores on every row, so the wait before a row's first-step
+    // collision covers only that row's loads, not the stores and the loads
+    // issued after them.
+    auto row_step = [&](int k, int it, S (&raw)[L::Q]) {
+        finish_a(it, raw);
+        load_a(min(k + 2, ye), raw);
+        wave_lds_sync();
+        if (b_lane) {
+            C h[L::Q];
+            static_for<L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int c = K::cls(i);
+                const int slot = (it - c) % K::slots(c);
+                h[i] = Codec<S>::load(&lds[lds_at(c, K::index(i), slot, lane - L::ex(i))]);
+            });
+            C rho, ux, uy, uz;
+            collide<L, C, true>(h, r, rho, ux, uy, uz);
+            const unsigned row = (unsigned)wrapc(k - 1, g.ny);
+            static_for<L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                Codec<S>::template store<NT>(at(dst, g, i, row, bxg), h[i]);
+            });
+        }
+        wave_lds_sync();
+    };
+    // A rows ys - 1 and ys first (ye >= ys + 1), then rows ys + 1 ... ye
+    // with B, alternating between two register sets
+    S raw0[L::Q], raw1[L::Q];
+    load_a(ys - 1, raw0);
+    load_a(ys, raw1);
+    finish_a(0, raw0);
+    load_a(ys + 1, raw0);
+    finish_a(1, raw1);
+    load_a(min(ys + 2, ye), raw1);
+    // pairs of rows with one exit test, so that the back edge is the only
+    // path into the loop head
+    const int nb = ye - ys;
+    int k = ys + 1, it = 2;
+    for (int p = 0; p < (nb >> 1); ++p, k += 2, it += 2) {
+        row_step(k, it, raw0);
+        row_step(k + 1, it + 1, raw1);
+    }
+    if (nb & 1) row_step(k, it, raw0);
 }
 
 } // namespace ptrt

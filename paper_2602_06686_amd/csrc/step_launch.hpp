@@ -34,17 +34,47 @@ void launch_step_d3q27(const StepLaunch &a);
 // returns false (nothing launched) otherwise.
 // *pass_bytes: the algorithmic HBM bytes of the pass (the state read once
 // and written once).
+bool launch_step2_d2q9(const StepLaunch &a, double *pass_bytes);
 bool launch_step2_d3q19(const StepLaunch &a, double *pass_bytes);
 bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes);
 
 template <class L>
 bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
 {
-    if constexpr (L::D != 3) {
+    if (a.has_mask || a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II)
         return false;
+    if constexpr (L::D == 2) {
+        // measured against one step per pass: a gain from 768^2 nodes in
+        // FP32 and from 512^2 in FP64; none in FP16 / BF16, whose one-step
+        // kernel moves half the bytes for the same arithmetic
+        const long long nodes = (long long)a.g.nx * a.g.ny;
+        if (a.storage == PTRT_F16 || a.storage == PTRT_BF16) return false;
+        if (nodes < (a.storage == PTRT_F64 ? (1LL << 18) : (1LL << 19))) return false;
+        dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
+            using S = typename decltype(st)::type;
+            using C = typename Codec<S>::compute;
+            using SH = Step2Shape2D<S>;
+            // strips of BX columns (the last may be partial), chunks of 8
+            // rows, four single-strip waves per workgroup (measured best at
+            // 2048^2 and 4096^2 in FP16, FP32 and FP64)
+            constexpr int YC = 8, NW = 4;
+            const int strips = (a.g.nx + SH::BX - 1) / SH::BX;
+            const int tasks = strips * ((a.g.ny + YC - 1) / YC);
+            if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * L::Q * sizeof(S);
+            const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
+            const dim3 grid((tasks + NW - 1) / NW, 1, 1);
+            if (a.nt)
+                hipLaunchKernelGGL((k_step2_2d<S, true, NW>), grid, dim3(SH::W * NW), 0,
+                                   a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
+                                   tasks);
+            else
+                hipLaunchKernelGGL((k_step2_2d<S, false, NW>), grid, dim3(SH::W * NW), 0,
+                                   a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
+                                   tasks);
+            return PTRT_OK;
+        });
+        return true;
     } else {
-        if (a.has_mask || a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II)
-            return false;
         bool launched = false;
         dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
             using S = typename decltype(st)::type;
@@ -60,7 +90,7 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                 const dim3 block(64 * SH::WAVES, 1, 1);
                 // the state read once and written once: the first step's
                 // halo re-reads are L2 traffic when neighbouring columns run
-                // on one XCD (measured: HBM reads 1.06x the state)
+                // on one XCD (measured: HBM reads 1.03x the state)
                 if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * a.g.nz * L::Q * sizeof(S);
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
                 if (a.nt)

@@ -1,9 +1,10 @@
-"""Two steps per pass (temporal blocking through LDS, D3Q19 FP32): the
-kernel must give the same populations, bit for bit, as one step per pass,
-for odd and even step counts and through the graph-replay path of small
-lattices; ineligible configurations (other storage types and lattices,
-solids, force, nx not a multiple of 64) fall back to one step per pass.  One eligible case is also checked against the
-FP64 oracle."""
+"""Two steps per pass (temporal blocking through LDS: D3Q19 FP32, and D2Q9
+in every storage type): the kernel must give the same populations, bit for
+bit, as one step per pass, for odd and even step counts, ragged strips and
+row chunks, and through the graph-replay path of small lattices;
+ineligible configurations (other storage types and lattices, solids, nx not
+a multiple of 64 in 3D) fall back to one step per pass.  Eligible cases are
+also checked against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -39,6 +40,71 @@ def test_two_steps_per_pass_bitwise(lat, storage, shape, steps):
     a = _run(lat, shape, storage, steps, 1)
     b = _run(lat, shape, storage, steps, 2)
     assert np.array_equal(a, b)
+
+
+# D2Q9 (two steps per pass from 2^19 nodes in FP32 and 2^18 in FP64):
+# strips of 62 columns (the last partial when nx is not a multiple), chunks
+# of 8 rows (the last partial), the periodic wrap crossing both, and the
+# degenerate widths 2 and 3 and heights 1, 2 and 4
+D2_CASES = [
+    ("f32", (1, 523, 1010)), ("f32", (1, 1, 600000)), ("f32", (1, 2, 300000)),
+    ("f32", (1, 200000, 3)), ("f32", (1, 9000, 62)), ("f64", (1, 515, 520)),
+    ("f64", (1, 200000, 2)), ("f64", (1, 4, 70000))]
+
+
+@pytest.mark.parametrize("storage,shape", D2_CASES)
+@pytest.mark.parametrize("steps", [1, 2, 7, 40])
+def test_two_steps_per_pass_d2q9_bitwise(storage, shape, steps):
+    print_case("D2Q9 steps per pass 2 vs 1", storage, shape, steps)
+    a = _run(0, shape, storage, steps, 1)
+    b = _run(0, shape, storage, steps, 2)
+    assert np.array_equal(a, b)
+
+
+def _last_pass(shape, storage, mask=None):
+    nz, ny, nx = shape
+    with P.Lattice(0, nx, ny, nz, 0.6, 0.25, storage=storage, solid_mask=mask) as G:
+        G.init_equilibrium(np.ones(shape), np.zeros((2,) + shape))
+        G.step(4)
+        return G.last_pass()
+
+
+def test_two_steps_per_pass_d2q9_used_where_it_pays():
+    """The pass covers two steps from the measured sizes on, in FP32 and
+    FP64 only, with or without a body force, and one step with solids."""
+    print_case("D2Q9 last pass: sizes, storage types, force, solids")
+    assert _last_pass((1, 512, 1024), "f32") == (2, 2.0 * 1024 * 512 * 9 * 4)
+    assert _last_pass((1, 511, 1024), "f32")[0] == 1
+    assert _last_pass((1, 512, 512), "f64") == (2, 2.0 * 512 * 512 * 9 * 8)
+    assert _last_pass((1, 256, 256), "f64")[0] == 1
+    for st in ("f16", "bf16"):
+        assert _last_pass((1, 1024, 1024), st)[0] == 1
+    mask = np.zeros((1, 512, 1024), dtype=np.uint8)
+    mask[0, 0, :] = 1
+    assert _last_pass((1, 512, 1024), "f32", mask=mask)[0] == 1
+    f = [2e-5, -1e-5, 0]
+    shape = (1, 600, 1000)
+    assert np.array_equal(_run(0, shape, "f32", 9, 1, force=f), _run(0, shape, "f32", 9, 2, force=f))
+
+
+def test_two_steps_per_pass_d2q9_matches_oracle():
+    print_case("D2Q9 steps per pass 2, FP64 520x510 with force vs oracle, 60 steps")
+    nz, ny, nx = n = (1, 510, 520)
+    rng = np.random.default_rng(13)
+    rho, u = I.random_fields(rng, n, umax=0.05)
+    u = u[:2]
+    with P.Lattice(0, nx, ny, nz, 0.58, 0.25, storage="f64", force=[1e-5, 2e-6, 0]) as G:
+        G.init_equilibrium(rho, u)
+        G.step(60)
+        assert G.last_pass()[0] == 2
+        hg = G.populations()
+    ora = O.Lattice(O.D2Q9, nx, ny, nz, 0.58, 0.25, g=[1e-5, 2e-6, 0], nthreads=8)
+    ora.init_equilibrium(rho, u)
+    ora.step(60)
+    ho = ora.populations()
+    err = np.abs(hg - ho).max() / np.abs(ho).max()
+    print(f"D2Q9 two steps per pass, 60 steps, max rel population error {err:.3e}", flush=True)
+    assert err < 1e-12
 
 
 def test_two_steps_per_pass_large_bitwise():
