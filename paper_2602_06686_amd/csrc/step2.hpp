@@ -11,12 +11,16 @@
 // (x, y, z) - e_i: from plane k when e_iz = -1, k - 1 when e_iz = 0 and
 // k - 2 when e_iz = +1, so LDS holds the e_z = -1 directions of one plane,
 // the e_z = 0 directions of two planes and the e_z = +1 directions of three
-// (38 direction planes of 66 x (BY + 2) nodes on D3Q19).  The loads of the
-// next plane's first step are issued before the current plane's second
-// step, so their latency overlaps it.  The A values pass
-// through the storage type exactly as they would through HBM, so two steps
-// of this kernel equal two steps of k_step bit for bit.  A chunk recomputes
-// the A planes just below and above it (ZC + 2 A planes for ZC B planes).
+// (38 direction planes of 66 x (BY + 2) nodes on D3Q19).  The workgroup
+// barriers order LDS only, so the loads of the next plane stay in flight
+// across them.  The A values pass through the storage type exactly as they
+// would through HBM, so two steps of this kernel equal two steps of k_step
+// bit for bit.  A chunk recomputes the A planes just below and above it
+// (ZC + 2 A planes for ZC B planes).  Measured alternatives that lost: a
+// second register set of loads, forcing the next plane's loads ahead of
+// the second step, BY = 8, 10 or 12, writing the e_z >= 0 classes to LDS
+// late (24 instead of 38 direction planes, three or four workgroups per
+// CU), and separate code paths for the row and halo tasks.
 #pragma once
 
 #include "kernels.hpp"
@@ -208,8 +212,11 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
             });
             C rho, ux, uy, uz;
             collide_ptrt<L, C>(h, r, rho, ux, uy, uz);
+            // past ny (the last workgroup row when BY does not divide ny)
+            // the wrapped row is computed again: the same values as its
+            // own workgroup writes
             const int gz = wrapc(k - 1, g.nz);
-            const unsigned row = (unsigned)gz * (unsigned)g.ny + (unsigned)(y0 + w);
+            const unsigned row = (unsigned)gz * (unsigned)g.ny + (unsigned)wrapc(y0 + w, g.ny);
             static_for<L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 Codec<S>::template store<NT>(at(dst, g, i, row, x0 + lane), h[i]);

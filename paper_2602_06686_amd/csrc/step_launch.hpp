@@ -81,12 +81,13 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
             using C = typename Codec<S>::compute;
             using SH = Step2Shape<L, S>;
             if constexpr (SH::available) {
-                if (a.g.nx % SH::BX != 0 || a.g.ny % SH::BY != 0) return PTRT_OK;
+                if (a.g.nx % SH::BX != 0 || a.g.ny < SH::BY) return PTRT_OK;
                 // z chunks: enough workgroups to fill the chip several times
-                const long long cols = (long long)(a.g.nx / SH::BX) * (a.g.ny / SH::BY);
+                const int rows = (a.g.ny + SH::BY - 1) / SH::BY;
+                const long long cols = (long long)(a.g.nx / SH::BX) * rows;
                 int zc = a.g.nz;
                 while (zc > 8 && cols * ((a.g.nz + zc - 1) / zc) < 1024) zc = (zc + 1) / 2;
-                const dim3 grid(a.g.nx / SH::BX, a.g.ny / SH::BY, (a.g.nz + zc - 1) / zc);
+                const dim3 grid(a.g.nx / SH::BX, rows, (a.g.nz + zc - 1) / zc);
                 const dim3 block(64 * SH::WAVES, 1, 1);
                 // the state read once and written once: the first step's
                 // halo re-reads are L2 traffic when neighbouring columns run
