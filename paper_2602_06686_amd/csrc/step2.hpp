@@ -16,9 +16,10 @@
 // across them.  The A values pass through the storage type exactly as they
 // would through HBM, so two steps of this kernel equal two steps of k_step
 // bit for bit.  A chunk recomputes the A planes just below and above it
-// (ZC + 2 A planes for ZC B planes).  Measured alternatives that lost: a
-// second register set of loads, forcing the next plane's loads ahead of
-// the second step, BY = 8, 10 or 12, writing the e_z >= 0 classes to LDS
+// (ZC + 2 A planes for ZC B planes).  Measured alternatives that lost:
+// forcing the next plane's loads ahead of the second step, BY = 8, 10 or
+// 12, a second copy of the halo task on the wave without a second task,
+// writing the e_z >= 0 classes to LDS
 // late (24 instead of 38 direction planes, three or four workgroups per
 // CU), and separate code paths for the row and halo tasks.
 #pragma once
