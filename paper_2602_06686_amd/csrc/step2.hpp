@@ -21,7 +21,10 @@
 // 12, a second copy of the halo task on the wave without a second task,
 // writing the e_z >= 0 classes to LDS
 // late (24 instead of 38 direction planes, three or four workgroups per
-// CU), and separate code paths for the row and halo tasks.
+// CU), separate code paths for the row and halo tasks, and keeping in LDS
+// only the 64 x 4 values per direction that the second step reads (39 KB,
+// three workgroups per CU: no faster at 256^3 or 512^3 for any chunk
+// length).
 #pragma once
 
 #include "kernels.hpp"
