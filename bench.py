@@ -317,12 +317,27 @@ def cpu_baseline(n=256, steps=12):
     L = O.Lattice(O.D3Q19, n, n, n, prm["tau_plus"], 0.25)
     L.init_equilibrium(rho, u)
     del rho, u
+    cores = O.max_threads()
     t0 = time.perf_counter()
     L.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": O.max_threads(),
+    del L
+    # the same oracle on one thread: two steps of a 96^3 lattice after one
+    # untimed step (which also touches the memory)
+    n1, s1 = 96, 2
+    prm1 = I.tgv3d_params(n1)
+    rho, u = I.tgv3d(n1, 0.05)
+    L1 = O.Lattice(O.D3Q19, n1, n1, n1, prm1["tau_plus"], 0.25, nthreads=1)
+    L1.init_equilibrium(rho, u)
+    L1.step(1)
+    t1 = time.perf_counter()
+    L1.step(s1)
+    dt1 = time.perf_counter() - t1
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
-            "sample": f"{steps} steps of the same {n}^3 D3Q19 lattice (FP64 C oracle, OpenMP over nodes), {dt:.1f} s"}
+            "sample": f"{steps} steps of the same {n}^3 D3Q19 lattice (FP64 C oracle, OpenMP over nodes), {dt:.1f} s",
+            "value_one_core": n1 ** 3 * s1 / dt1 / 1e6,
+            "sample_one_core": f"{s1} steps of a {n1}^3 D3Q19 lattice on one thread, {dt1:.1f} s"}
 
 
 def copy_calibration(torch, stream, nbytes=1 << 30):
@@ -334,6 +349,20 @@ def copy_calibration(torch, stream, nbytes=1 << 30):
             b.copy_(a)
     torch.cuda.synchronize()
     return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}
+
+
+def stream_rate(torch, stream, nbytes=1 << 30, reps=10):
+    """Read + write bytes per second of a plain streaming kernel, PyTorch's
+    elementwise multiply by 1 over a 1 GiB FP32 tensor (its vectorised
+    kernel streams faster than the runtime's copy): the bandwidth a simple
+    HBM-bound kernel reaches here, beside the 8 TB/s peak."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        ms, _ = timed_steps(torch, stream,
+                            lambda n: [torch.mul(a, 1.0, out=b) for _ in range(n)], reps, 2)
+    del a, b
+    return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
 def traffic_from_profile():
@@ -441,6 +470,12 @@ def main():
             "one_step_roofline_mlups": one_step_roof_mlups,
             "mlups_over_one_step_roofline": head["mlups"] / one_step_roof_mlups,
             "traffic_source": traffic_note}
+    ref = stream_rate(torch, stream)
+    roof["stream_reference_gbs"] = ref
+    roof["stream_reference"] = ("torch.mul(a, 1.0, out=b) over 1 GiB FP32 on the same stream, "
+                                "read + write bytes per second")
+    roof["achieved_over_stream_reference"] = head["pass_gbs"] / ref
+    roof["one_step_roofline_at_stream_reference_mlups"] = ref * 1e9 / head["bytes_per_node"] / 1e6
     cpu = None
     if not args.no_cpu:
         log("CPU baseline (oracle)")
