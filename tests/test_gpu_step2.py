@@ -32,6 +32,7 @@ def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5):
 @pytest.mark.parametrize("lat,storage,shape", [
     (1, "f32", (6, 8, 64)), (1, "f32", (7, 16, 128)), (1, "f32", (2, 8, 64)),
     (1, "f32", (3, 12, 64)), (1, "f32", (4, 10, 64)), (1, "f32", (3, 13, 128)), (1, "f32", (5, 6, 64)),
+    (1, "f32", (4, 32, 64)), (1, "f32", (3, 64, 128)), (1, "f32", (2, 16, 192)),
     (1, "f16", (5, 16, 64)), (1, "bf16", (9, 8, 128)),
     (2, "f16", (9, 8, 64)), (2, "bf16", (4, 12, 64))])
 @pytest.mark.parametrize("steps", [1, 2, 7, 40])
