@@ -264,8 +264,10 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// (eight waves per SIMD: FP32 fits in 64 VGPRs; measured +1.5 % at 4096^2)
 template <class S, bool NT, int NW>
 __global__ void __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(8, 8)))
 k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
            Coef<D2Q9, typename Codec<S>::compute> r, int yc, int strips, int tasks)
 {

@@ -56,23 +56,25 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
             using S = typename decltype(st)::type;
             using C = typename Codec<S>::compute;
             using SH = Step2Shape2D<S>;
-            // strips of BX columns (the last may be partial), chunks of 8
-            // rows, four single-strip waves per workgroup (measured best at
-            // 2048^2 and 4096^2 in FP16, FP32 and FP64)
-            constexpr int YC = 8, NW = 4;
-            const int strips = (a.g.nx + SH::BX - 1) / SH::BX;
-            const int tasks = strips * ((a.g.ny + YC - 1) / YC);
-            if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * L::Q * sizeof(S);
-            const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
-            const dim3 grid((tasks + NW - 1) / NW, 1, 1);
-            if (a.nt)
-                hipLaunchKernelGGL((k_step2_2d<S, true, NW>), grid, dim3(SH::W * NW), 0,
-                                   a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
-                                   tasks);
-            else
-                hipLaunchKernelGGL((k_step2_2d<S, false, NW>), grid, dim3(SH::W * NW), 0,
-                                   a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
-                                   tasks);
+            if constexpr (sizeof(S) != 2) { // FP16 / BF16: not used (above)
+                // strips of BX columns (the last may be partial), chunks of 8
+                // rows, four single-strip waves per workgroup (measured best at
+                // 2048^2 and 4096^2 in FP16, FP32 and FP64)
+                constexpr int YC = 8, NW = 4;
+                const int strips = (a.g.nx + SH::BX - 1) / SH::BX;
+                const int tasks = strips * ((a.g.ny + YC - 1) / YC);
+                if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * L::Q * sizeof(S);
+                const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
+                const dim3 grid((tasks + NW - 1) / NW, 1, 1);
+                if (a.nt)
+                    hipLaunchKernelGGL((k_step2_2d<S, true, NW>), grid, dim3(SH::W * NW), 0,
+                                       a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
+                                       tasks);
+                else
+                    hipLaunchKernelGGL((k_step2_2d<S, false, NW>), grid, dim3(SH::W * NW), 0,
+                                       a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
+                                       tasks);
+            }
             return PTRT_OK;
         });
         return true;
