@@ -298,8 +298,34 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     auto lds_at = [](int c, int idx, int slot, int a) {
         return (K::region(c) + slot * K::count(c) + idx) * W + a;
     };
-    auto load_a = [&](int k, S (&raw)[L::Q]) {
-        pull<L, S, false>(src, nullptr, g, ax, wrapc(k, g.ny), 0, raw, [](const S *p) { return *p; });
+    // Addresses: the byte offsets of the rows in use are kept in a window
+    // that moves by one row per step (one new row offset per row), each
+    // population adds its direction's fixed offset, and the x part is a
+    // per-lane 32-bit byte offset fixed for the task: little scalar work
+    // per row.  Rows wrap periodically: the prologue takes remainders, the
+    // window then advances its last row by one with a wrap test.
+    const unsigned rmask = (1u << g.lr) - 1u;
+    auto row_off_w = [&](int u) -> size_t { // u in [0, ny)
+        return ((size_t)((unsigned)u >> g.lr) * (size_t)g.tile +
+                (size_t)(((unsigned)u & rmask) * (unsigned)g.pitch)) *
+               sizeof(S);
+    };
+    auto wrapr = [&](int v) { return ((v % g.ny) + g.ny) % g.ny; };
+    auto row_off = [&](int row) -> size_t { return row_off_w(wrapr(row)); };
+    const size_t dir_bytes = (size_t)g.plane * sizeof(S);
+    const unsigned xo_m = (unsigned)wrapc(ax - 1, g.nx) * (unsigned)sizeof(S);
+    const unsigned xo_0 = (unsigned)ax * (unsigned)sizeof(S);
+    const unsigned xo_p = (unsigned)wrapc(ax + 1, g.nx) * (unsigned)sizeof(S);
+    // first-step pull of a row, given the offsets of the rows below, at and
+    // above it: population i of (x, y) comes from (x, y) - e_i
+    auto load_a = [&](size_t om, size_t o0, size_t op, S (&raw)[L::Q]) {
+        const char *sb = reinterpret_cast<const char *>(src);
+        static_for<L::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const size_t ro = L::ey(i) == 1 ? om : (L::ey(i) == -1 ? op : o0);
+            const unsigned xo = L::ex(i) == 1 ? xo_m : (L::ex(i) == -1 ? xo_p : xo_0);
+            raw[i] = *reinterpret_cast<const S *>(sb + ro + (size_t)i * dir_bytes + xo);
+        });
     };
     auto finish_a = [&](int it, const S (&raw)[L::Q]) {
         C h[L::Q];
@@ -320,14 +346,16 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     const int bxg = x0 - 1 + lane;
     const bool b_lane = lane >= 1 && lane <= BX && bxg < g.nx;
     // one row of the march: finish A of row k from raw, refill raw with the
-    // loads of row k + 2 (two rows in flight; past the chunk the last row
-    // is loaded again), B of row k - 1.  Every wave issues the same loads
-    // and stores on every row, so the wait before a row's first-step
-    // collision covers only that row's loads, not the stores and the loads
-    // issued after them.
+    // loads of row k + 2 (two rows in flight; past the chunk they are not
+    // used), B of row k - 1.  Every wave issues the same loads and stores on
+    // every row, so the wait before a row's first-step collision covers
+    // only that row's loads, not the stores and the loads issued after
+    // them.  o[j] is the offset of row k - 1 + j.
+    size_t o[5];
+    int r4; // row of o[4], wrapped
     auto row_step = [&](int k, int it, S (&raw)[L::Q]) {
         finish_a(it, raw);
-        load_a(min(k + 2, ye), raw);
+        load_a(o[2], o[3], o[4], raw);
         wave_lds_sync();
         if (b_lane) {
             C h[L::Q];
@@ -339,23 +367,32 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
             });
             C rho, ux, uy, uz;
             collide<L, C, true>(h, r, rho, ux, uy, uz);
-            const unsigned row = (unsigned)wrapc(k - 1, g.ny);
+            char *db = reinterpret_cast<char *>(dst) + o[0];
             static_for<L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                Codec<S>::template store<NT>(at(dst, g, i, row, bxg), h[i]);
+                Codec<S>::template store<NT>(
+                    reinterpret_cast<S *>(db + (size_t)i * dir_bytes + xo_0), h[i]);
             });
         }
         wave_lds_sync();
+        o[0] = o[1];
+        o[1] = o[2];
+        o[2] = o[3];
+        o[3] = o[4];
+        r4 = r4 + 1 == g.ny ? 0 : r4 + 1;
+        o[4] = row_off_w(r4);
     };
     // A rows ys - 1 and ys first (ye >= ys + 1), then rows ys + 1 ... ye
     // with B, alternating between two register sets
     S raw0[L::Q], raw1[L::Q];
-    load_a(ys - 1, raw0);
-    load_a(ys, raw1);
+    load_a(row_off(ys - 2), row_off(ys - 1), row_off(ys), raw0);
+    load_a(row_off(ys - 1), row_off(ys), row_off(ys + 1), raw1);
     finish_a(0, raw0);
-    load_a(ys + 1, raw0);
+    for (int j = 0; j < 5; ++j) o[j] = row_off(ys + j);
+    r4 = wrapr(ys + 4);
+    load_a(o[0], o[1], o[2], raw0);
     finish_a(1, raw1);
-    load_a(min(ys + 2, ye), raw1);
+    load_a(o[1], o[2], o[3], raw1);
     // pairs of rows with one exit test, so that the back edge is the only
     // path into the loop head
     const int nb = ye - ys;
