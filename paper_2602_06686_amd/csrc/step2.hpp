@@ -17,14 +17,12 @@
 // would through HBM, so two steps of this kernel equal two steps of k_step
 // bit for bit.  A chunk recomputes the A planes just below and above it
 // (ZC + 2 A planes for ZC B planes).  Measured alternatives that lost:
-// forcing the next plane's loads ahead of the second step, BY = 8, 10 or
-// 12, a second copy of the halo task on the wave without a second task,
-// writing the e_z >= 0 classes to LDS
-// late (24 instead of 38 direction planes, three or four workgroups per
-// CU), separate code paths for the row and halo tasks, and keeping in LDS
-// only the 64 x 4 values per direction that the second step reads (39 KB,
-// three workgroups per CU: no faster at 256^3 or 512^3 for any chunk
-// length).
+// forcing the next plane's loads ahead of the second step; BY = 8, 10 or
+// 12; a second copy of the halo task on the wave without a second task;
+// writing the e_z >= 0 classes to LDS after the second step (24 instead of
+// 38 direction planes, three or four workgroups per CU); separate code
+// paths for the row and halo tasks; keeping in LDS only the 64 x 4 values
+// per direction that the second step reads (three workgroups per CU).
 #pragma once
 
 #include "kernels.hpp"
@@ -233,13 +231,9 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     }
 }
 
-} // namespace ptrt
-
-namespace ptrt {
-
 // Two fused steps per pass for D2Q9 without solids (the 2D counterpart of
-// k_step2): a workgroup is one wave that owns a strip of 62 columns and a
-// chunk of rows and marches up through its rows.  For row k the wave
+// k_step2): each wave of a workgroup owns a strip of 62 columns and a
+// chunk of rows and marches up through its rows, on its own.  For row k the wave
 // computes the first step (A) on 64 nodes, columns x0 - 1 ... x0 + 62 (the
 // strip plus a one-column halo on each side), pulling from HBM, and keeps
 // the results in LDS in the storage type; lanes 1 ... 62 then compute the
