@@ -165,12 +165,13 @@ int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
 /* Steps per pass over the populations (1 or 2; default 2).  With 2, pairs
  * of steps run as one kernel that keeps the first step's results in LDS
  * (temporal blocking) where the configuration allows it and it measured
- * faster: no solid nodes, periodic boundaries, PTRT_MODEL_PTRT and
- * PTRT_FORCING_SCHEME2, and either D3Q19 in FP32 with nx a multiple of 64
- * and ny >= 4, or D2Q9 in FP32 with nx ny >= 2^19 or in FP64 with
- * nx ny >= 2^18; every other case, and an odd last step, runs one step per
- * pass.  Results are bit-identical either way.  Allowed at any time (waits
- * for the handle's stream). */
+ * faster: periodic boundaries, PTRT_MODEL_PTRT and PTRT_FORCING_SCHEME2,
+ * and either D3Q19 in FP32 without solid nodes, nx a multiple of 64 and
+ * ny >= 4, or D2Q9 in FP32 with nx ny >= 2^19 without solid nodes, or
+ * D2Q9 in FP64 with nx ny >= 2^18, with solid nodes near the rows of at
+ * most 30 % of the kernel's 8-row chunks; every other case, and an odd last
+ * step, runs one step per pass.  Results are bit-identical either way.
+ * Allowed at any time (waits for the handle's stream). */
 int ptrt_set_steps_per_pass(ptrt_ctx *ctx, int steps);
 
 /* The most recent kernel pass enqueued by ptrt_step: *steps = the steps it

@@ -37,6 +37,9 @@ struct ptrt_ctx {
     bool has_mask = false;
     std::vector<uint8_t> h_mask, h_near;
     uint8_t *d_mask = nullptr, *d_near = nullptr;
+    // D2Q9 with solids: two-step tasks without / with solids near their rows
+    int *d_tasks = nullptr; // plain tasks, then masked tasks
+    int n_plain = 0, n_masked = 0;
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     double2 *d_partials = nullptr;
@@ -133,6 +136,27 @@ int ensure_allocated(ptrt_ctx *c)
         c->h_near = near_solid_rows(c->h_mask.data(), c->nx, c->ny, c->nz);
         HIPCHK(c, hipMalloc(&c->d_near, c->h_near.size()));
         HIPCHK(c, hipMemcpy(c->d_near, c->h_near.data(), c->h_near.size(), hipMemcpyHostToDevice));
+        if (c->lattice == PTRT_D2Q9) {
+            // the two-step kernel's (strip, chunk) tasks, split by whether a
+            // row ys - 1 ... ye of the chunk has a solid within one row
+            using SH = Step2Shape2D<float>;
+            const int strips = (c->nx + SH::BX - 1) / SH::BX;
+            const int chunks = (c->ny + SH::YC - 1) / SH::YC;
+            std::vector<int> plain, masked;
+            for (int by = 0; by < chunks; ++by) {
+                const int ys = by * SH::YC, ye = std::min(ys + SH::YC, c->ny);
+                bool near = false;
+                for (int y = ys - 1; y <= ye && !near; ++y)
+                    near = c->h_near[(size_t)(((y % c->ny) + c->ny) % c->ny)] != 0;
+                for (int bx = 0; bx < strips; ++bx) (near ? masked : plain).push_back(by * strips + bx);
+            }
+            c->n_plain = (int)plain.size();
+            c->n_masked = (int)masked.size();
+            plain.insert(plain.end(), masked.begin(), masked.end());
+            HIPCHK(c, hipMalloc(&c->d_tasks, sizeof(int) * plain.size()));
+            HIPCHK(c, hipMemcpy(c->d_tasks, plain.data(), sizeof(int) * plain.size(),
+                                hipMemcpyHostToDevice));
+        }
     }
     const dim3 gg = gather_grid(c, c->nz);
     c->nparts = gg.x * gg.y * gg.z;
@@ -306,6 +330,12 @@ StepLaunch step_args(const ptrt_ctx *c, hipStream_t s)
     a.dst = c->buf[c->cur ^ 1];
     a.mask = c->d_mask;
     a.near = c->d_near;
+    if (c->d_tasks) {
+        a.tasks_plain = c->d_tasks;
+        a.tasks_masked = c->d_tasks + c->n_plain;
+        a.n_plain = c->n_plain;
+        a.n_masked = c->n_masked;
+    }
     a.g = geom(c);
     a.tau_plus = c->tau_plus;
     a.Lambda = c->Lambda;
@@ -655,6 +685,7 @@ int ptrt_destroy(ptrt_ctx *c)
         if (c->buf[k]) (void)hipFree(c->buf[k]);
     if (c->d_mask) (void)hipFree(c->d_mask);
     if (c->d_near) (void)hipFree(c->d_near);
+    if (c->d_tasks) (void)hipFree(c->d_tasks);
     for (auto &gx : c->graph)
         if (gx) (void)hipGraphExecDestroy(gx);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);

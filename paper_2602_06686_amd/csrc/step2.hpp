@@ -29,8 +29,10 @@
 
 namespace ptrt {
 
-// Direction classes along the marching axis (z in 3D, y in 2D).
-template <class L, int AXIS = L::D - 1>
+// Direction classes along the marching axis (z in 3D, y in 2D).  BB: the
+// second step also reads the first step's values of its own node (halfway
+// bounce-back), so the e_y = -1 class keeps the plane below too.
+template <class L, int AXIS = L::D - 1, bool BB = false>
 struct Step2Classes {
     // class of a direction: 0 (e_z = -1), 1 (e_z = 0), 2 (e_z = +1)
     __host__ __device__ static constexpr int cls(int i)
@@ -51,7 +53,7 @@ struct Step2Classes {
     }
     // slots kept per class: plane k (e_z = -1), k - 1 and k (e_z = 0),
     // k - 2 ... k (e_z = +1)
-    __host__ __device__ static constexpr int slots(int c) { return c + 1; }
+    __host__ __device__ static constexpr int slots(int c) { return BB && c == 0 ? 2 : c + 1; }
     __host__ __device__ static constexpr int region(int c)
     {
         int off = 0;
@@ -242,11 +244,15 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
 // node comes from the A node (x, y) - e_i: row k when e_iy = -1, k - 1 when
 // e_iy = 0, k - 2 when e_iy = +1 (1 + 2 + 3 slots of three directions,
 // 18 rows of 64 values).  Bit-identical to two one-step launches.
-template <class S>
+template <class S, bool MASK = false>
 struct Step2Shape2D {
-    static constexpr int W = 64;         // A nodes per row (one wave)
-    static constexpr int BX = W - 2;     // interior columns per strip
-    static constexpr size_t lds_bytes = (size_t)Step2Classes<D2Q9>::planes * W * sizeof(S);
+    static constexpr int W = 64;     // A nodes per row (one wave)
+    static constexpr int BX = W - 2; // interior columns per strip
+    // rows per chunk and waves (independent strips) per workgroup: measured
+    // best at 2048^2 and 4096^2 in FP32 and FP64
+    static constexpr int YC = 8, NW = 4;
+    using K = Step2Classes<D2Q9, 1, MASK>;
+    static constexpr size_t lds_bytes = (size_t)K::planes * W * sizeof(S);
 };
 
 // Order of the LDS accesses of one wave (its lanes exchange values only
@@ -258,17 +264,26 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Task t of the launch is (strip, chunk) = tasks[t] % strips, tasks[t] /
+// strips, or t itself without a list.  MASK: the tasks read the mask
+// (halfway bounce-back; tasks whose rows ys - 1 ... ye hold no solid within
+// one row run the MASK = false kernel): the first step pulls the node's own
+// opposite population where the source is solid, the second step likewise
+// from the first step's values of its own node, and solid second-step
+// nodes are not stored (as in the one-step kernel).
 // (eight waves per SIMD: FP32 fits in 64 VGPRs; measured +1.5 % at 4096^2)
-template <class S, bool NT, int NW>
+template <class S, bool NT, int NW, bool MASK>
 __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
-           Coef<D2Q9, typename Codec<S>::compute> r, int yc, int strips, int tasks)
+k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+           const int *__restrict__ task_list, Geom g, Coef<D2Q9, typename Codec<S>::compute> r,
+           int yc, int strips, int tasks)
 {
     using L = D2Q9;
     using C = typename Codec<S>::compute;
-    using K = Step2Classes<D2Q9>;
-    constexpr int W = Step2Shape2D<S>::W, BX = Step2Shape2D<S>::BX;
+    using SH = Step2Shape2D<S, MASK>;
+    using K = typename SH::K;
+    constexpr int W = SH::W, BX = SH::BX;
     __shared__ S lds_all[NW * K::planes * W];
 
     // the NW waves of a workgroup run independent tasks (strip, chunk),
@@ -276,8 +291,9 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     int wg, unused_y, unused_z;
     xcd_block(wg, unused_y, unused_z);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int task = wg * NW + w;
-    if (task >= tasks) return;
+    const int t = wg * NW + w;
+    if (t >= tasks) return;
+    const int task = task_list ? task_list[t] : t;
     S *lds = lds_all + w * (K::planes * W);
     const int bx = task % strips, by = task / strips;
     const int x0 = bx * BX;
@@ -289,36 +305,60 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         return v < 0 ? v + n : v;
     };
     const int ax = wrapc(x0 - 1 + lane, g.nx); // this lane's A column
+    const int axm = wrapc(ax - 1, g.nx), axp = wrapc(ax + 1, g.nx);
     auto lds_at = [](int c, int idx, int slot, int a) {
         return (K::region(c) + slot * K::count(c) + idx) * W + a;
     };
-    // Addresses: the byte offsets of the rows in use are kept in a window
-    // that moves by one row per step (one new row offset per row), each
-    // population adds its direction's fixed offset, and the x part is a
-    // per-lane 32-bit byte offset fixed for the task: little scalar work
-    // per row.  Rows wrap periodically: the prologue takes remainders, the
-    // window then advances its last row by one with a wrap test.
+    auto wrapr = [&](int v) { return ((v % g.ny) + g.ny) % g.ny; };
+
+    // Addresses: the rows in use (k - 2 ... k + 3 while the march is at row
+    // k) sit in a window, o[j] their byte offsets and rw[j] their indices,
+    // that advances by one row per step (one new row offset per row, with
+    // a wrap test); each population adds its direction's fixed offset, and
+    // the lane's x offsets are fixed for the task: little scalar work per
+    // row.
     const unsigned rmask = (1u << g.lr) - 1u;
     auto row_off_w = [&](int u) -> size_t { // u in [0, ny)
         return ((size_t)((unsigned)u >> g.lr) * (size_t)g.tile +
                 (size_t)(((unsigned)u & rmask) * (unsigned)g.pitch)) *
                sizeof(S);
     };
-    auto wrapr = [&](int v) { return ((v % g.ny) + g.ny) % g.ny; };
-    auto row_off = [&](int row) -> size_t { return row_off_w(wrapr(row)); };
     const size_t dir_bytes = (size_t)g.plane * sizeof(S);
-    const unsigned xo_m = (unsigned)wrapc(ax - 1, g.nx) * (unsigned)sizeof(S);
+    const unsigned xo_m = (unsigned)axm * (unsigned)sizeof(S);
     const unsigned xo_0 = (unsigned)ax * (unsigned)sizeof(S);
-    const unsigned xo_p = (unsigned)wrapc(ax + 1, g.nx) * (unsigned)sizeof(S);
-    // first-step pull of a row, given the offsets of the rows below, at and
-    // above it: population i of (x, y) comes from (x, y) - e_i
-    auto load_a = [&](size_t om, size_t o0, size_t op, S (&raw)[L::Q]) {
+    const unsigned xo_p = (unsigned)axp * (unsigned)sizeof(S);
+    size_t o[6];
+    int rw[6];
+    auto shift = [&]() {
+        static_for<5>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            o[j] = o[j + 1];
+            rw[j] = rw[j + 1];
+        });
+        rw[5] = rw[4] + 1 == g.ny ? 0 : rw[4] + 1;
+        o[5] = row_off_w(rw[5]);
+    };
+    // solid flag of node (column of lane + dx, window row j)
+    auto solid = [&](int j, int dx) -> bool {
+        const int x = dx < 0 ? axm : (dx > 0 ? axp : ax);
+        return mask[(size_t)rw[j] * (unsigned)g.nx + (unsigned)x] != 0;
+    };
+    // first-step pull of window row J: population i of (x, y) comes from
+    // (x, y) - e_i, or from the node's own opposite population when that
+    // source is solid
+    auto load_a = [&](auto jc, S (&raw)[L::Q]) {
+        constexpr int J = decltype(jc)::value;
         const char *sb = reinterpret_cast<const char *>(src);
         static_for<L::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const size_t ro = L::ey(i) == 1 ? om : (L::ey(i) == -1 ? op : o0);
+            constexpr int js = J - L::ey(i);
             const unsigned xo = L::ex(i) == 1 ? xo_m : (L::ex(i) == -1 ? xo_p : xo_0);
-            raw[i] = *reinterpret_cast<const S *>(sb + ro + (size_t)i * dir_bytes + xo);
+            const char *p = sb + o[js] + (size_t)i * dir_bytes + xo;
+            if constexpr (MASK && i != 0) {
+                if (solid(js, -L::ex(i)))
+                    p = sb + o[J] + (size_t)L::opp(i) * dir_bytes + xo_0;
+            }
+            raw[i] = *reinterpret_cast<const S *>(p);
         });
     };
     auto finish_a = [&](int it, const S (&raw)[L::Q]) {
@@ -341,27 +381,35 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     const bool b_lane = lane >= 1 && lane <= BX && bxg < g.nx;
     // one row of the march: finish A of row k from raw, refill raw with the
     // loads of row k + 2 (two rows in flight; past the chunk they are not
-    // used), B of row k - 1.  Every wave issues the same loads and stores on
-    // every row, so the wait before a row's first-step collision covers
-    // only that row's loads, not the stores and the loads issued after
-    // them.  o[j] is the offset of row k - 1 + j.
-    size_t o[5];
-    int r4; // row of o[4], wrapped
-    auto row_step = [&](int k, int it, S (&raw)[L::Q]) {
+    // used), B of row k - 1 (window row 1).  Every wave issues the same
+    // loads and stores on every row, so the wait before a row's first-step
+    // collision covers only that row's loads, not the stores and the loads
+    // issued after them.
+    auto row_step = [&](int it, S (&raw)[L::Q]) {
         finish_a(it, raw);
-        load_a(o[2], o[3], o[4], raw);
+        load_a(std::integral_constant<int, 4>{}, raw);
         wave_lds_sync();
-        if (b_lane) {
+        bool store = b_lane;
+        if constexpr (MASK) store = store && !solid(1, 0);
+        if (store) {
             C h[L::Q];
             static_for<L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 constexpr int c = K::cls(i);
                 const int slot = (it - c) % K::slots(c);
-                h[i] = Codec<S>::load(&lds[lds_at(c, K::index(i), slot, lane - L::ex(i))]);
+                int at_i = lds_at(c, K::index(i), slot, lane - L::ex(i));
+                if constexpr (MASK && i != 0) {
+                    // own node's first-step value of the opposite direction,
+                    // row k - 1 (iteration it - 1)
+                    constexpr int io = L::opp(i), co = K::cls(io);
+                    if (solid(1 - L::ey(i), -L::ex(i)))
+                        at_i = lds_at(co, K::index(io), (it - 1) % K::slots(co), lane);
+                }
+                h[i] = Codec<S>::load(&lds[at_i]);
             });
             C rho, ux, uy, uz;
             collide<L, C, true>(h, r, rho, ux, uy, uz);
-            char *db = reinterpret_cast<char *>(dst) + o[0];
+            char *db = reinterpret_cast<char *>(dst) + o[1];
             static_for<L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 Codec<S>::template store<NT>(
@@ -369,33 +417,32 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, Geom g,
             });
         }
         wave_lds_sync();
-        o[0] = o[1];
-        o[1] = o[2];
-        o[2] = o[3];
-        o[3] = o[4];
-        r4 = r4 + 1 == g.ny ? 0 : r4 + 1;
-        o[4] = row_off_w(r4);
+        shift();
     };
-    // A rows ys - 1 and ys first (ye >= ys + 1), then rows ys + 1 ... ye
-    // with B, alternating between two register sets
+    // window at rows ys - 2 ... ys + 3: A rows ys - 1 and ys (no B yet, ye >=
+    // ys + 1), then rows ys + 1 ... ye with B, alternating between two
+    // register sets
+    for (int j = 0; j < 6; ++j) {
+        rw[j] = wrapr(ys - 2 + j);
+        o[j] = row_off_w(rw[j]);
+    }
     S raw0[L::Q], raw1[L::Q];
-    load_a(row_off(ys - 2), row_off(ys - 1), row_off(ys), raw0);
-    load_a(row_off(ys - 1), row_off(ys), row_off(ys + 1), raw1);
+    load_a(std::integral_constant<int, 1>{}, raw0);
+    load_a(std::integral_constant<int, 2>{}, raw1);
     finish_a(0, raw0);
-    for (int j = 0; j < 5; ++j) o[j] = row_off(ys + j);
-    r4 = wrapr(ys + 4);
-    load_a(o[0], o[1], o[2], raw0);
+    load_a(std::integral_constant<int, 3>{}, raw0);
     finish_a(1, raw1);
-    load_a(o[1], o[2], o[3], raw1);
+    load_a(std::integral_constant<int, 4>{}, raw1);
+    shift(); // window at rows ys - 1 ... ys + 4 = k - 2 ... k + 3, k = ys + 1
     // pairs of rows with one exit test, so that the back edge is the only
     // path into the loop head
     const int nb = ye - ys;
-    int k = ys + 1, it = 2;
-    for (int p = 0; p < (nb >> 1); ++p, k += 2, it += 2) {
-        row_step(k, it, raw0);
-        row_step(k + 1, it + 1, raw1);
+    int it = 2;
+    for (int p = 0; p < (nb >> 1); ++p, it += 2) {
+        row_step(it, raw0);
+        row_step(it + 1, raw1);
     }
-    if (nb & 1) row_step(k, it, raw0);
+    if (nb & 1) row_step(it, raw0);
 }
 
 } // namespace ptrt

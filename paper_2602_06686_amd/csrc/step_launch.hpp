@@ -26,6 +26,10 @@ struct StepLaunch {
     void *phi = nullptr; // Phi field in the compute type (FORCE_II_G)
     bool open = false;   // D2Q9 inlet / outlet in x (values in g)
     hipStream_t stream = nullptr;
+    // D2Q9 with solids, two steps per pass: the (strip, chunk) tasks without
+    // and with a solid within one row of their rows (Step2Shape2D)
+    const int *tasks_plain = nullptr, *tasks_masked = nullptr;
+    int n_plain = 0, n_masked = 0;
 };
 
 void launch_step_d2q9(const StepLaunch &a);
@@ -43,8 +47,7 @@ bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes);
 template <class L>
 bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
 {
-    if (a.has_mask || a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II)
-        return false;
+    if (a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II) return false;
     if constexpr (L::D == 2) {
         // measured against one step per pass: a gain from 768^2 nodes in
         // FP32 and from 512^2 in FP64; none in FP16 / BF16, whose one-step
@@ -52,33 +55,60 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
         const long long nodes = (long long)a.g.nx * a.g.ny;
         if (a.storage == PTRT_F16 || a.storage == PTRT_BF16) return false;
         if (nodes < (a.storage == PTRT_F64 ? (1LL << 18) : (1LL << 19))) return false;
+        // with solids: the tasks near solids take the masked kernel, a
+        // second launch slower per node than one step per pass, so the pass
+        // is used in FP64 while they are at most 30 % of the tasks
+        // (measured, one step -> two: channel 4096^2 42.3 -> 61.4 GLUPS,
+        // 2048^2 40.6 -> 50.8; an obstacle over 1/8 of the rows 42.7 ->
+        // 61.1); in FP32 it gained 10 % at 4096^2 and lost 3 % at 2048^2
+        if (a.has_mask) {
+            const int all = a.n_plain + a.n_masked;
+            if (a.storage != PTRT_F64 || all == 0 || !a.tasks_plain || !a.tasks_masked)
+                return false;
+            if (a.n_masked > 0.3 * all) return false;
+        }
         dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
             using S = typename decltype(st)::type;
             using C = typename Codec<S>::compute;
             using SH = Step2Shape2D<S>;
             if constexpr (sizeof(S) != 2) { // FP16 / BF16: not used (above)
-                // strips of BX columns (the last may be partial), chunks of 8
-                // rows, four single-strip waves per workgroup (measured best at
-                // 2048^2 and 4096^2 in FP16, FP32 and FP64)
-                constexpr int YC = 8, NW = 4;
+                // strips of BX columns (the last may be partial), chunks of
+                // YC rows, NW single-strip waves per workgroup
+                constexpr int YC = SH::YC, NW = SH::NW;
                 const int strips = (a.g.nx + SH::BX - 1) / SH::BX;
                 const int tasks = strips * ((a.g.ny + YC - 1) / YC);
-                if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * L::Q * sizeof(S);
+                // the state read once and written once (plus the mask bytes)
+                if (pass_bytes)
+                    *pass_bytes = (2.0 * L::Q * sizeof(S) + (a.has_mask ? 1.0 : 0.0)) *
+                                  a.g.nx * a.g.ny;
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
-                const dim3 grid((tasks + NW - 1) / NW, 1, 1);
-                if (a.nt)
-                    hipLaunchKernelGGL((k_step2_2d<S, true, NW>), grid, dim3(SH::W * NW), 0,
-                                       a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
-                                       tasks);
-                else
-                    hipLaunchKernelGGL((k_step2_2d<S, false, NW>), grid, dim3(SH::W * NW), 0,
-                                       a.stream, (const S *)a.src, (S *)a.dst, a.g, r, YC, strips,
-                                       tasks);
+                auto go = [&](auto mc, const int *list, int n) {
+                    constexpr bool M = decltype(mc)::value;
+                    if (n == 0) return;
+                    const dim3 grid((n + NW - 1) / NW, 1, 1);
+                    if (a.nt)
+                        hipLaunchKernelGGL((k_step2_2d<S, true, NW, M>), grid, dim3(SH::W * NW), 0,
+                                           a.stream, (const S *)a.src, (S *)a.dst, a.mask, list,
+                                           a.g, r, YC, strips, n);
+                    else
+                        hipLaunchKernelGGL((k_step2_2d<S, false, NW, M>), grid, dim3(SH::W * NW),
+                                           0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
+                                           list, a.g, r, YC, strips, n);
+                };
+                if (a.has_mask) {
+                    if constexpr (sizeof(S) == 8) {
+                        go(std::false_type{}, a.tasks_plain, a.n_plain);
+                        go(std::true_type{}, a.tasks_masked, a.n_masked);
+                    }
+                } else {
+                    go(std::false_type{}, nullptr, tasks);
+                }
             }
             return PTRT_OK;
         });
         return true;
     } else {
+        if (a.has_mask) return false;
         bool launched = false;
         dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
             using S = typename decltype(st)::type;

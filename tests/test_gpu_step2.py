@@ -72,7 +72,8 @@ def _last_pass(shape, storage, mask=None):
 
 def test_two_steps_per_pass_d2q9_used_where_it_pays():
     """The pass covers two steps from the measured sizes on, in FP32 and
-    FP64 only, with or without a body force, and one step with solids."""
+    FP64 only, with or without a body force; with solids in FP64 while few
+    rows are near them."""
     print_case("D2Q9 last pass: sizes, storage types, force, solids")
     assert _last_pass((1, 512, 1024), "f32") == (2, 2.0 * 1024 * 512 * 9 * 4)
     assert _last_pass((1, 511, 1024), "f32")[0] == 1
@@ -82,10 +83,80 @@ def test_two_steps_per_pass_d2q9_used_where_it_pays():
         assert _last_pass((1, 1024, 1024), st)[0] == 1
     mask = np.zeros((1, 512, 1024), dtype=np.uint8)
     mask[0, 0, :] = 1
+    # with solids, FP64 only: the state and the mask bytes
+    assert _last_pass((1, 512, 1024), "f64", mask=mask) == (2, (2.0 * 9 * 8 + 1) * 1024 * 512)
     assert _last_pass((1, 512, 1024), "f32", mask=mask)[0] == 1
+    for m in _d2_masks():
+        assert _last_pass(m.shape, "f64", mask=m)[0] == 2
+    # solids near most rows: one step per pass
+    dense = (np.random.default_rng(4).random((1, 512, 1024)) < 0.01).astype(np.uint8)
+    assert _last_pass((1, 512, 1024), "f64", mask=dense)[0] == 1
     f = [2e-5, -1e-5, 0]
     shape = (1, 600, 1000)
     assert np.array_equal(_run(0, shape, "f32", 9, 1, force=f), _run(0, shape, "f32", 9, 2, force=f))
+
+
+def _d2_masks():
+    """Solid layouts with few rows near solids (where two steps per pass are
+    used): channel walls on the periodic y seam, a band of random solids
+    (some next to each other, across chunk and strip borders), a square
+    obstacle, and a solid column on the periodic x seam with blocks at a
+    strip border and in the last, partial strip."""
+    rng = np.random.default_rng(21)
+    out = []
+    m = np.zeros((1, 600, 1000), dtype=np.uint8)
+    m[0, 0, :] = m[0, -1, :] = 1
+    out.append(m)
+    m = np.zeros((1, 515, 520), dtype=np.uint8)
+    m[0, 100:141, :] = rng.random((41, 520)) < 0.05
+    out.append(m)
+    m = np.zeros((1, 1030, 520), dtype=np.uint8)
+    m[0, 500:533, 240:273] = 1
+    out.append(m)
+    m = np.zeros((1, 700, 801), dtype=np.uint8)
+    m[0, 300:321, 0] = 1
+    m[0, 300:310, 700:800] = 1
+    m[0, 7:9, 61:63] = 1
+    out.append(m)
+    return out
+
+
+@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("steps", [2, 7, 40])
+def test_two_steps_per_pass_d2q9_solids_bitwise(case, steps):
+    """With solids the pass covers two steps in FP64 (below)."""
+    storage, mask = "f64", _d2_masks()[case]
+    print_case("D2Q9 with solids, steps per pass 2 vs 1", storage, mask.shape, steps)
+    a = _run(0, mask.shape, storage, steps, 1, mask=mask, force=[1e-6, 0, 0])
+    b = _run(0, mask.shape, storage, steps, 2, mask=mask, force=[1e-6, 0, 0])
+    fluid = np.broadcast_to(mask == 0, a.shape)
+    assert np.array_equal(a[fluid], b[fluid])
+
+
+def test_two_steps_per_pass_d2q9_channel_matches_oracle():
+    print_case("D2Q9 channel, steps per pass 2, FP64 520x510 vs oracle, 40 steps")
+    nz, ny, nx = n = (1, 510, 520)
+    mask = np.zeros(n, dtype=np.uint8)
+    mask[0, 0, :] = mask[0, -1, :] = 1
+    mask[0, 200:220, 100:130] = 1
+    rng = np.random.default_rng(17)
+    rho, u = I.random_fields(rng, n, umax=0.03)
+    u = u[:2]
+    g = [2e-5, 0, 0]
+    with P.Lattice(0, nx, ny, nz, 0.62, 3 / 16, storage="f64", force=g, solid_mask=mask) as G:
+        G.init_equilibrium(rho, u)
+        G.step(40)
+        assert G.last_pass()[0] == 2
+        rg, ug = G.moments()
+    ora = O.Lattice(O.D2Q9, nx, ny, nz, 0.62, 3 / 16, g=g, solid=mask, nthreads=8)
+    ora.init_equilibrium(rho, u)
+    ora.step(40)
+    ro, uo = ora.moments()
+    fl = mask == 0
+    err = np.abs(ug[:2][:, fl] - uo[:2][:, fl]).max() / np.abs(uo[:2][:, fl]).max()
+    print(f"D2Q9 channel two steps per pass, 40 steps, max rel velocity error {err:.3e}", flush=True)
+    assert err < 1e-12
+    assert np.abs(rg[fl] - ro[fl]).max() < 1e-12
 
 
 def test_two_steps_per_pass_d2q9_matches_oracle():
