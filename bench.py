@@ -10,8 +10,9 @@ one-launch-per-lattice comparison), and the two D2Q9 single-lattice
 configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64),
 the collision-model comparison, D3Q27 (hybrid P-TRT, FP32 / FP16, and
 its comparison models) on the 256^3 vortex, the forcing schemes (Scheme II
-with the cubic correction, Scheme I) against the default, and the square
-cylinder with open boundaries and the momentum-exchange force.
+with the cubic correction, Scheme I) against the default, a 4096^2 FP64
+channel with walls (one and two steps per pass), and the square cylinder
+with open boundaries and the momentum-exchange force.
 
 ``roofline`` describes the dominant kernel of the headline: the pass that
 runs two D3Q19 FP32 steps per launch (first step over each workgroup's
@@ -19,10 +20,12 @@ column and halo, kept in LDS; second step written back).  Its algorithmic
 HBM bytes per launch (reported by the library: the state read once and
 written once, 2 * 19 * 4 bytes per node for two steps) over the average
 launch time, against the 8 TB/s HBM peak; beside it the MLUPS as a fraction
-of the one-step roofline (8 TB/s over 2 * 19 * 4 bytes per node and step).  ``traffic`` is read from the
-committed rocprofv3 counter summary when it was taken on the current kernel
-sources, else null.  ``cpu_baseline`` times the FP64 C oracle on twelve steps
-of the same 256^3 lattice on the host cores.
+of the one-step roofline (8 TB/s over 2 * 19 * 4 bytes per node and step),
+and a plain streaming kernel's bandwidth measured beside it.  ``traffic`` is
+read from the committed rocprofv3 counter summary when it was taken on the
+current kernel sources, else null.  ``cpu_baseline`` times the FP64 C oracle
+on twelve steps of the same 256^3 lattice on the host cores (and on one
+thread).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only FORM]
                        [--no-cpu] [--copy-calibration]
@@ -273,6 +276,29 @@ def form_forcing(P, torch, stream, steps, warmup):
     return out
 
 
+def form_channel(P, torch, stream, steps, warmup):
+    """Force-driven channel (the Sec. 3.3 geometry, at a bandwidth-sized
+    lattice): D2Q9 FP64 4096^2, halfway bounce-back walls at y = 0 and
+    ny - 1, Lambda = 3/16, tau+ = 0.8, g_x = 1e-8; one step per pass and
+    two steps per pass (the wall rows' tasks through the masked kernel)."""
+    import numpy as np
+    n = 4096
+    mask = np.zeros((1, n, n), dtype=np.uint8)
+    mask[0, 0, :] = mask[0, -1, :] = 1
+    out = {"workload": "D2Q9 P-TRT FP64 4096^2 channel (walls at y = 0 and 4095, g_x = 1e-8, "
+                       "tau+ = 0.8, Lambda = 3/16), from rest"}
+
+    def init():
+        return np.ones((1, n, n)), np.zeros((2, 1, n, n))
+
+    for spp in (1, 2):
+        r = bench_single(P, torch, stream, P.PTRT_D2Q9, (1, n, n), "f64", init, 0.8, 3 / 16,
+                         steps, warmup, force=[1e-8, 0, 0], mask=mask, steps_per_pass=spp)
+        out[f"steps_per_pass_{spp}"] = r
+    out["two_over_one"] = out["steps_per_pass_2"]["mlups"] / out["steps_per_pass_1"]["mlups"]
+    return out
+
+
 def form_cylinder(P, torch, stream, steps, warmup):
     """Creeping flow past a square cylinder (Sec. 3.4): D2Q9, D = 21,
     L = 50 D (1050^2 nodes), moving-wall inlet, Zou-He outlet, periodic y,
@@ -384,7 +410,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default=None,
                     help="run one form: d3q19_256_f32, d3q19_512, batch, dsl2048, models, "
-                         "d3q27, forcing, cylinder, tgv64")
+                         "d3q27, forcing, channel, cylinder, tgv64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -444,6 +470,11 @@ def main():
         log("forcing schemes")
         forms["forcing_fp32"] = form_forcing(P, torch, stream, max(20, K // 2), max(2, W // 2))
         log(json.dumps(forms["forcing_fp32"]))
+    if only in (None, "channel"):
+        log("D2Q9 FP64 channel 4096^2")
+        forms["channel_d2q9_4096_f64"] = form_channel(P, torch, stream, max(20, K // 2),
+                                                      max(2, W // 2))
+        log(json.dumps(forms["channel_d2q9_4096_f64"]))
     if only in (None, "cylinder"):
         log("square cylinder")
         forms["cylinder_d2q9"] = form_cylinder(P, torch, stream, K, W)
