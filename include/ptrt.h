@@ -166,8 +166,8 @@ int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
  * of steps run as one kernel that keeps the first step's results in LDS
  * (temporal blocking) where the configuration allows it and it measured
  * faster: periodic boundaries, PTRT_MODEL_PTRT and PTRT_FORCING_SCHEME2,
- * and either D3Q19 in FP32 without solid nodes, nx a multiple of 64 and
- * ny >= 4, or D2Q9 in FP32 with nx ny >= 2^19 without solid nodes, or
+ * and either D3Q19 in FP32 or FP64 without solid nodes, nx a multiple of
+ * 64 and ny >= 4, or D2Q9 in FP32 with nx ny >= 2^19 without solid nodes, or
  * D2Q9 in FP64 with nx ny >= 2^18, with solid nodes near the rows of at
  * most 30 % of the kernel's 8-row chunks; every other case, and an odd last
  * step, runs one step per pass.  Results are bit-identical either way.

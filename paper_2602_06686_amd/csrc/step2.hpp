@@ -67,10 +67,11 @@ struct Step2Classes {
 template <class L, class S>
 struct Step2Shape {
     static constexpr int BX = 64;
-    // measured: a gain for D3Q19 in FP32 only; in FP16 / BF16 (and on D3Q27)
-    // the one-step kernel is already near its instruction-issue limit and
-    // the halo's extra collisions outweigh the halved traffic
-    static constexpr int BY = (sizeof(S) == 4 && L::Q == 19) ? 4 : 0;
+    // measured: a gain for D3Q19 in FP32 and FP64 (one workgroup per CU,
+    // +18 % at 256^3); in FP16 / BF16 and on D3Q27 the one-step kernel is
+    // already near its instruction-issue limit and the halo's extra
+    // collisions outweigh the halved traffic
+    static constexpr int BY = ((sizeof(S) == 4 || sizeof(S) == 8) && L::Q == 19) ? 4 : 0;
     static constexpr int AX = BX + 2, AY = BY + 2, AP = AX * AY;
     // one wave per interior row; the AY + 1 first-step tasks (AY rows and
     // the halo columns) are shared out over them, at most two per wave
@@ -78,7 +79,7 @@ struct Step2Shape {
     using K = Step2Classes<L>;
     static constexpr size_t lds_bytes = (size_t)K::planes * AP * sizeof(S);
     static constexpr bool available =
-        BY >= 3 && sizeof(S) <= 4 && lds_bytes <= 163840 && AY + 1 <= 2 * WAVES;
+        BY >= 3 && lds_bytes <= 163840 && AY + 1 <= 2 * WAVES;
 };
 
 // Workgroup barrier that orders the LDS accesses only: the global loads in

@@ -1,5 +1,5 @@
-"""Two steps per pass (temporal blocking through LDS: D3Q19 FP32, and D2Q9
-in every storage type): the kernel must give the same populations, bit for
+"""Two steps per pass (temporal blocking through LDS: D3Q19 in FP32 and
+FP64, D2Q9 in FP32 and FP64): the kernel must give the same populations, bit for
 bit, as one step per pass, for odd and even step counts, ragged strips and
 row chunks, and through the graph-replay path of small lattices;
 ineligible configurations (other storage types and lattices, solids, nx not
@@ -33,6 +33,7 @@ def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5):
     (1, "f32", (6, 8, 64)), (1, "f32", (7, 16, 128)), (1, "f32", (2, 8, 64)),
     (1, "f32", (3, 12, 64)), (1, "f32", (4, 10, 64)), (1, "f32", (3, 13, 128)), (1, "f32", (5, 6, 64)),
     (1, "f32", (4, 32, 64)), (1, "f32", (3, 64, 128)), (1, "f32", (2, 16, 192)),
+    (1, "f64", (4, 8, 64)), (1, "f64", (3, 10, 128)),
     (1, "f16", (5, 16, 64)), (1, "bf16", (9, 8, 128)),
     (2, "f16", (9, 8, 64)), (2, "bf16", (4, 12, 64))])
 @pytest.mark.parametrize("steps", [1, 2, 7, 40])
