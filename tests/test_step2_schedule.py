@@ -1,0 +1,202 @@
+"""The schedule of the two-steps-per-pass kernels (csrc/step2.hpp), checked on
+the CPU: which first-step value each second-step population reads, in
+which LDS slot of its direction class it is held, which halo a workgroup
+recomputes, and (D2Q9 with solids) where halfway bounce-back takes the
+node's own first-step value instead.  The schedule is emulated here in
+NumPy with the oracle's collision as the per-node map, and the second
+step's pulled populations must equal the oracle's state after two steps
+(pulled = pre-collision) exactly.  CPU only: the kernels themselves are
+checked bit for bit against one step per pass in test_gpu_step2.py.
+
+Schedule (one workgroup, marching along the last axis a: z in 3D, y in 2D):
+for plane k it computes the first step (A) on its tile plus a one-node halo
+and keeps each direction i in the slots of its class c = e_ia + 1 (1, 2 and
+3 slots; 2, 2, 3 with solids), slot = plane index mod slots(c); the second
+step (B) for plane k - 1 reads direction i of node x from A node x - e_i in
+plane k - 1 - e_ia, i.e. slot (it - c) mod slots(c).
+"""
+import numpy as np
+import pytest
+
+import lbm_inputs as I
+from oracle import ptrt as O
+
+
+def _classes(e, axis, bb=False):
+    c = e[:, axis].astype(int) + 1
+    slots = [2 if bb else 1, 2, 3]
+    count = [int((c == k).sum()) for k in range(3)]
+    index = [int((c[:i] == c[i]).sum()) for i in range(len(c))]
+    region = [0, slots[0] * count[0], slots[0] * count[0] + slots[1] * count[1]]
+    planes = sum(s * n for s, n in zip(slots, count))
+    return c, slots, count, index, region, planes
+
+
+def _collide(lat, h, tp, lam):
+    """Oracle collision of populations h [Q, n] (pre -> post)."""
+    tm = 0.5 + lam / (tp - 0.5)
+    return O.collide(lat, np.ascontiguousarray(h.T), None, tp, tau_minus=tm).T
+
+
+def _start(lat, shape, tp, lam, solid=None, seed=3):
+    """Oracle lattice at t = 0 and the stored (post-collision) state whose
+    pull gives its populations: collide them once at every node."""
+    rng = np.random.default_rng(seed)
+    rho, u = I.random_fields(rng, shape, umax=0.05)
+    if lat == O.D2Q9:
+        u = u[:2]
+    ora = O.Lattice(lat, shape[2], shape[1], shape[0], tp, lam, solid=solid)
+    ora.init_equilibrium(rho, u)
+    f = ora.populations()
+    Q = f.shape[0]
+    stored = _collide(lat, f.reshape(Q, -1), tp, lam).reshape(f.shape)
+    ora.step(2)
+    return stored, ora.populations()
+
+
+def _two_step_3d(stored, e, tp, lam, BY, zc):
+    """k_step2 schedule on D3Q19: 64 x BY columns, chunks of zc planes."""
+    Q, nz, ny, nx = stored.shape
+    BX, AX, AY = 64, 66, BY + 2
+    AP = AX * AY
+    cls, slots, count, index, region, planes = _classes(e, 2)
+    out = np.full(stored.shape, np.nan)
+    ex, ey, ez = (e[:, a].astype(int) for a in range(3))
+
+    def at(c, i_idx, slot, a):
+        v = (region[c] + slot * count[c] + i_idx) * AP + a
+        assert np.all((v >= 0) & (v < planes * AP))
+        return v
+
+    # A nodes: rows 0..AY-1 at ax = 1..64, then the two halo columns
+    ax = np.concatenate([np.tile(np.arange(1, 65), AY), np.zeros(AY, int), np.full(AY, AX - 1)])
+    ay = np.concatenate([np.repeat(np.arange(AY), 64), np.arange(AY), np.arange(AY)])
+    for bz in range((nz + zc - 1) // zc):
+        for by in range((ny + BY - 1) // BY):
+            for bx in range(nx // BX):
+                x0, y0, zs = bx * BX, by * BY, bz * zc
+                ze = min(zs + zc, nz)
+                lds = np.full(planes * AP, np.nan)
+                for it, k in enumerate(range(zs - 1, ze + 1)):
+                    gx, gy, gz = (x0 - 1 + ax) % nx, (y0 - 1 + ay) % ny, k % nz
+                    raw = np.stack([stored[i, (gz - ez[i]) % nz, (gy - ey[i]) % ny,
+                                           (gx - ex[i]) % nx] for i in range(Q)])
+                    post = _collide(O.D3Q19, raw, tp, lam)
+                    for i in range(Q):
+                        lds[at(cls[i], index[i], it % slots[cls[i]], ay * AX + ax)] = post[i]
+                    if k < zs + 1:
+                        continue
+                    bxl = np.tile(np.arange(64), BY)
+                    byl = np.repeat(np.arange(BY), 64)
+                    h = np.stack([lds[at(cls[i], index[i], (it - cls[i]) % slots[cls[i]],
+                                         (byl + 1 - ey[i]) * AX + (bxl + 1 - ex[i]))]
+                                  for i in range(Q)])
+                    out[:, (k - 1) % nz, (y0 + byl) % ny, x0 + bxl] = h
+    return out
+
+
+@pytest.mark.parametrize("nx,ny,nz,BY,zc", [
+    (64, 8, 5, 4, 2), (128, 4, 3, 4, 8), (64, 10, 3, 4, 8), (64, 13, 2, 4, 1), (64, 8, 6, 8, 3)])
+def test_d3q19_schedule(nx, ny, nz, BY, zc):
+    e, _, _ = O.lattice(O.D3Q19)
+    stored, ref = _start(O.D3Q19, (nz, ny, nx), 0.7, 0.25)
+    got = _two_step_3d(stored, e, 0.7, 0.25, BY, zc)
+    assert not np.isnan(got).any()
+    assert np.abs(got - ref).max() < 1e-14
+
+
+def _two_step_2d(stored, e, opp, tp, lam, yc, solid=None, near_only=True):
+    """k_step2_2d schedule on D2Q9: one wave per strip of 62 columns (64 A
+    nodes), chunks of yc rows; with solids, bounce-back in both steps."""
+    Q, _, ny, nx = stored.shape
+    st = stored[:, 0]
+    W, BX = 64, 62
+    bb = solid is not None
+    cls, slots, count, index, region, planes = _classes(e, 1, bb)
+    ex, ey = e[:, 0].astype(int), e[:, 1].astype(int)
+    m = solid[0] if bb else np.zeros((ny, nx), bool)
+    solid_row = m.any(axis=1)
+    near = np.array([solid_row[(y - 1) % ny] or solid_row[y] or solid_row[(y + 1) % ny]
+                     for y in range(ny)])
+    out = np.full((Q, ny, nx), np.nan)
+    lanes = np.arange(W)
+
+    def at(c, i_idx, slot, a):
+        v = (region[c] + slot * count[c] + i_idx) * W + a
+        assert np.all((v >= 0) & (v < planes * W))
+        return v
+
+    for by in range((ny + yc - 1) // yc):
+        for bx in range((nx + BX - 1) // BX):
+            x0, ys = bx * BX, by * yc
+            ye = min(ys + yc, ny)
+            masked = bb and (not near_only or any(near[y % ny] for y in range(ys - 1, ye + 1)))
+            ax = (x0 - 1 + lanes) % nx
+            lds = np.full(planes * W, np.nan)
+            for it, k in enumerate(range(ys - 1, ye + 1)):
+                raw = np.empty((Q, W))
+                for i in range(Q):
+                    sy, sx = (k - ey[i]) % ny, (ax - ex[i]) % nx
+                    v = st[i, sy, sx].copy()
+                    if masked and i:
+                        s = m[sy, sx] != 0
+                        v[s] = st[opp[i], k % ny, ax][s]
+                    raw[i] = v
+                post = _collide(O.D2Q9, raw, tp, lam)
+                for i in range(Q):
+                    lds[at(cls[i], index[i], it % slots[cls[i]], lanes)] = post[i]
+                if k < ys + 1:
+                    continue
+                bl = np.arange(1, BX + 1)
+                bl = bl[x0 - 1 + bl < nx]
+                xb = ax[bl]
+                h = np.empty((Q, len(bl)))
+                for i in range(Q):
+                    c = cls[i]
+                    v = lds[at(c, index[i], (it - c) % slots[c], bl - ex[i])].copy()
+                    if masked and i:
+                        s = m[(k - 1 - ey[i]) % ny, (xb - ex[i]) % nx] != 0
+                        io = opp[i]
+                        v[s] = lds[at(cls[io], index[io], (it - 1) % slots[cls[io]], bl)][s]
+                    h[i] = v
+                if masked:
+                    h[:, m[(k - 1) % ny, xb] != 0] = np.nan
+                out[:, (k - 1) % ny, xb] = h
+    return out
+
+
+@pytest.mark.parametrize("ny,nx,yc", [(16, 64, 8), (37, 130, 8), (9, 200, 4), (1, 70, 8),
+                                      (2, 5, 8), (33, 17, 3), (30, 1, 8)])
+def test_d2q9_schedule(ny, nx, yc):
+    e, _, opp = O.lattice(O.D2Q9)
+    stored, ref = _start(O.D2Q9, (1, ny, nx), 0.7, 0.25)
+    got = _two_step_2d(stored, e, opp, 0.7, 0.25, yc)
+    assert not np.isnan(got).any()
+    assert np.abs(got - ref[:, 0]).max() < 1e-14
+
+
+def _masks():
+    rng = np.random.default_rng(0)
+    m1 = np.zeros((40, 130), np.uint8)
+    m1[0] = m1[-1] = 1
+    m2 = (rng.random((37, 70)) < 0.08).astype(np.uint8)
+    m3 = np.zeros((30, 62), np.uint8)
+    m3[10:15, 20:30] = 1
+    m3[:, 0] = 1
+    m4 = (rng.random((9, 17)) < 0.2).astype(np.uint8)
+    return [(m1, 8), (m2, 8), (m3, 8), (m4, 4)]
+
+
+@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("near_only", [True, False])
+def test_d2q9_schedule_solids(case, near_only):
+    """Bounce-back in both steps; the mask-free code on chunks with no
+    solid within one row (near_only) changes nothing."""
+    mask, yc = _masks()[case]
+    ny, nx = mask.shape
+    e, _, opp = O.lattice(O.D2Q9)
+    stored, ref = _start(O.D2Q9, (1, ny, nx), 0.8, 3 / 16, solid=mask[None])
+    got = _two_step_2d(stored, e, opp, 0.8, 3 / 16, yc, solid=mask[None], near_only=near_only)
+    fluid = mask == 0
+    assert not np.isnan(got[:, fluid]).any()
+    assert np.abs(got[:, fluid] - ref[:, 0][:, fluid]).max() < 1e-14
