@@ -141,10 +141,11 @@ int ensure_allocated(ptrt_ctx *c)
             // row ys - 1 ... ye of the chunk has a solid within one row
             using SH = Step2Shape2D<float>;
             const int strips = (c->nx + SH::BX - 1) / SH::BX;
-            const int chunks = (c->ny + SH::YC - 1) / SH::YC;
+            const int yc = step2_2d_rows(c->storage, c->nx, c->ny);
+            const int chunks = (c->ny + yc - 1) / yc;
             std::vector<int> plain, masked;
             for (int by = 0; by < chunks; ++by) {
-                const int ys = by * SH::YC, ye = std::min(ys + SH::YC, c->ny);
+                const int ys = by * yc, ye = std::min(ys + yc, c->ny);
                 bool near = false;
                 for (int y = ys - 1; y <= ye && !near; ++y)
                     near = c->h_near[(size_t)(((y % c->ny) + c->ny) % c->ny)] != 0;

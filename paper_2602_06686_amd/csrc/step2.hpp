@@ -249,9 +249,9 @@ template <class S, bool MASK = false>
 struct Step2Shape2D {
     static constexpr int W = 64;     // A nodes per row (one wave)
     static constexpr int BX = W - 2; // interior columns per strip
-    // rows per chunk and waves (independent strips) per workgroup: measured
-    // best at 2048^2 and 4096^2 in FP32 and FP64
-    static constexpr int YC = 8, NW = 4;
+    // waves (independent strips) per workgroup: measured best at 2048^2 and
+    // 4096^2 in FP32 and FP64 (rows per chunk: chosen per lattice)
+    static constexpr int NW = 4;
     using K = Step2Classes<D2Q9, 1, MASK>;
     static constexpr size_t lds_bytes = (size_t)K::planes * W * sizeof(S);
 };

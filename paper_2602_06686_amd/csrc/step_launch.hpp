@@ -44,17 +44,33 @@ bool launch_step2_d2q9(const StepLaunch &a, double *pass_bytes);
 bool launch_step2_d3q19(const StepLaunch &a, double *pass_bytes);
 bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes);
 
+// Rows per chunk of the D2Q9 two-step kernel for an nx x ny lattice.  A
+// wave computes the first step on yc + 2 rows to finish yc, so short chunks
+// repeat first-step work but give more tasks to spread over the chip;
+// measured (64^2 ... 4096^2, FP32 and FP64) best near 1600 tasks in FP32
+// and 800 in FP64 (a fifth of the waves the chip holds at once, 32 and 16
+// per CU as LDS allows), at most 9 rows (7 from 2^22 nodes on, 2 - 3 %
+// faster there), and never 4 or 8, which measured 5 - 15 % slower than 5
+// and 9 at 724^2 - 1024^2.
+inline int step2_2d_rows(int storage, int nx, int ny)
+{
+    const long long strips = (nx + Step2Shape2D<float>::BX - 1) / Step2Shape2D<float>::BX;
+    const long long target = storage == PTRT_F64 ? 800 : 1600;
+    const long long cap = (long long)nx * ny >= (1LL << 22) ? 7 : 9;
+    long long yc = std::min(cap, std::max(1LL, (strips * ny + target - 1) / target));
+    if (yc == 4 || yc == 8) ++yc;
+    return (int)yc;
+}
+
 template <class L>
 bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
 {
     if (a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II) return false;
     if constexpr (L::D == 2) {
-        // measured against one step per pass: a gain from 768^2 nodes in
-        // FP32 and from 512^2 in FP64; none in FP16 / BF16, whose one-step
-        // kernel moves half the bytes for the same arithmetic
-        const long long nodes = (long long)a.g.nx * a.g.ny;
+        // measured against one step per pass: a gain at every size in FP32
+        // and FP64 (64^2 ... 4096^2, 8 - 30 %); none in FP16 / BF16, whose
+        // one-step kernel moves half the bytes for the same arithmetic
         if (a.storage == PTRT_F16 || a.storage == PTRT_BF16) return false;
-        if (nodes < (a.storage == PTRT_F64 ? (1LL << 18) : (1LL << 19))) return false;
         // with solids: the tasks near solids take the masked kernel, a
         // second launch slower per node than one step per pass, so the pass
         // is used in FP64 while they are at most 30 % of the tasks
@@ -73,10 +89,12 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
             using SH = Step2Shape2D<S>;
             if constexpr (sizeof(S) != 2) { // FP16 / BF16: not used (above)
                 // strips of BX columns (the last may be partial), chunks of
-                // YC rows, NW single-strip waves per workgroup
-                constexpr int YC = SH::YC, NW = SH::NW;
+                // yc rows (the last may be partial), NW single-strip waves per
+                // workgroup
+                const int yc = step2_2d_rows(a.storage, a.g.nx, a.g.ny);
+                constexpr int NW = SH::NW;
                 const int strips = (a.g.nx + SH::BX - 1) / SH::BX;
-                const int tasks = strips * ((a.g.ny + YC - 1) / YC);
+                const int tasks = strips * ((a.g.ny + yc - 1) / yc);
                 // the state read once and written once (plus the mask bytes)
                 if (pass_bytes)
                     *pass_bytes = (2.0 * L::Q * sizeof(S) + (a.has_mask ? 1.0 : 0.0)) *
@@ -89,11 +107,11 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                     if (a.nt)
                         hipLaunchKernelGGL((k_step2_2d<S, true, NW, M>), grid, dim3(SH::W * NW), 0,
                                            a.stream, (const S *)a.src, (S *)a.dst, a.mask, list,
-                                           a.g, r, YC, strips, n);
+                                           a.g, r, yc, strips, n);
                     else
                         hipLaunchKernelGGL((k_step2_2d<S, false, NW, M>), grid, dim3(SH::W * NW),
                                            0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
-                                           list, a.g, r, YC, strips, n);
+                                           list, a.g, r, yc, strips, n);
                 };
                 if (a.has_mask) {
                     if constexpr (sizeof(S) == 8) {

@@ -44,14 +44,26 @@ def test_two_steps_per_pass_bitwise(lat, storage, shape, steps):
     assert np.array_equal(a, b)
 
 
-# D2Q9 (two steps per pass from 2^19 nodes in FP32 and 2^18 in FP64):
-# strips of 62 columns (the last partial when nx is not a multiple), chunks
-# of 8 rows (the last partial), the periodic wrap crossing both, and the
-# degenerate widths 2 and 3 and heights 1, 2 and 4
+# D2Q9 (two steps per pass in FP32 and FP64): strips of 62 columns (the
+# last partial when nx is not a multiple), chunks of 1 to 9 rows chosen by
+# size (the last partial; the chunk height of each case in the comment),
+# the periodic wrap crossing both, and the degenerate widths 1, 2 and 3 and
+# heights 1, 2 and 4
 D2_CASES = [
-    ("f32", (1, 523, 1010)), ("f32", (1, 1, 600000)), ("f32", (1, 2, 300000)),
-    ("f32", (1, 200000, 3)), ("f32", (1, 9000, 62)), ("f64", (1, 515, 520)),
-    ("f64", (1, 200000, 2)), ("f64", (1, 4, 70000))]
+    ("f32", (1, 523, 1010)),  # 6 rows
+    ("f32", (1, 1, 600000)), ("f32", (1, 2, 300000)),
+    ("f32", (1, 200000, 3)),  # 9
+    ("f32", (1, 9000, 62)),  # 6
+    ("f32", (1, 64, 64)), ("f32", (1, 37, 130)), ("f32", (1, 5, 1)),  # 1
+    ("f32", (1, 333, 500)),  # 2
+    ("f32", (1, 517, 530)),  # 3
+    ("f32", (1, 2049, 2048)),  # 7
+    ("f64", (1, 515, 520)),  # 6
+    ("f64", (1, 200000, 2)), ("f64", (1, 4, 70000)),
+    ("f64", (1, 64, 64)),  # 1
+    ("f64", (1, 301, 390)),  # 3
+    ("f64", (1, 453, 400)),  # 5 (4 is skipped)
+    ("f64", (1, 1023, 1000))]  # 9 (8 is skipped)
 
 
 @pytest.mark.parametrize("storage,shape", D2_CASES)
@@ -72,16 +84,17 @@ def _last_pass(shape, storage, mask=None):
 
 
 def test_two_steps_per_pass_d2q9_used_where_it_pays():
-    """The pass covers two steps from the measured sizes on, in FP32 and
-    FP64 only, with or without a body force; with solids in FP64 while few
-    rows are near them."""
+    """The pass covers two steps at every size in FP32 and FP64 only, with
+    or without a body force; with solids in FP64 while few rows are near
+    them."""
     print_case("D2Q9 last pass: sizes, storage types, force, solids")
     assert _last_pass((1, 512, 1024), "f32") == (2, 2.0 * 1024 * 512 * 9 * 4)
-    assert _last_pass((1, 511, 1024), "f32")[0] == 1
+    assert _last_pass((1, 3, 5), "f32") == (2, 2.0 * 5 * 3 * 9 * 4)
     assert _last_pass((1, 512, 512), "f64") == (2, 2.0 * 512 * 512 * 9 * 8)
-    assert _last_pass((1, 256, 256), "f64")[0] == 1
+    assert _last_pass((1, 64, 64), "f64")[0] == 2
     for st in ("f16", "bf16"):
         assert _last_pass((1, 1024, 1024), st)[0] == 1
+        assert _last_pass((1, 64, 64), st)[0] == 1
     mask = np.zeros((1, 512, 1024), dtype=np.uint8)
     mask[0, 0, :] = 1
     # with solids, FP64 only: the state and the mask bytes
@@ -102,7 +115,7 @@ def _d2_masks():
     used): channel walls on the periodic y seam, a band of random solids
     (some next to each other, across chunk and strip borders), a square
     obstacle, and a solid column on the periodic x seam with blocks at a
-    strip border and in the last, partial strip."""
+    strip border and in the last, partial strip; then small lattices."""
     rng = np.random.default_rng(21)
     out = []
     m = np.zeros((1, 600, 1000), dtype=np.uint8)
@@ -119,10 +132,17 @@ def _d2_masks():
     m[0, 300:310, 700:800] = 1
     m[0, 7:9, 61:63] = 1
     out.append(m)
+    # small lattices (chunks of 1 and 3 rows): channel walls, a random band
+    m = np.zeros((1, 64, 64), dtype=np.uint8)
+    m[0, 0, :] = m[0, -1, :] = 1
+    out.append(m)
+    m = np.zeros((1, 301, 390), dtype=np.uint8)
+    m[0, 150:170, :] = rng.random((20, 390)) < 0.1
+    out.append(m)
     return out
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 @pytest.mark.parametrize("steps", [2, 7, 40])
 def test_two_steps_per_pass_d2q9_solids_bitwise(case, steps):
     """With solids the pass covers two steps in FP64 (below)."""

@@ -166,7 +166,8 @@ def _two_step_2d(stored, e, opp, tp, lam, yc, solid=None, near_only=True):
 
 
 @pytest.mark.parametrize("ny,nx,yc", [(16, 64, 8), (37, 130, 8), (9, 200, 4), (1, 70, 8),
-                                      (2, 5, 8), (33, 17, 3), (30, 1, 8)])
+                                      (2, 5, 8), (33, 17, 3), (30, 1, 8), (1, 1, 1), (5, 1, 1),
+                                      (16, 64, 1), (9, 130, 2), (23, 70, 5), (20, 63, 9)])
 def test_d2q9_schedule(ny, nx, yc):
     e, _, opp = O.lattice(O.D2Q9)
     stored, ref = _start(O.D2Q9, (1, ny, nx), 0.7, 0.25)
@@ -184,10 +185,14 @@ def _masks():
     m3[10:15, 20:30] = 1
     m3[:, 0] = 1
     m4 = (rng.random((9, 17)) < 0.2).astype(np.uint8)
-    return [(m1, 8), (m2, 8), (m3, 8), (m4, 4)]
+    m5 = np.zeros((16, 64), np.uint8)
+    m5[0] = m5[-1] = 1
+    m6 = np.zeros((25, 70), np.uint8)
+    m6[10:14] = rng.random((4, 70)) < 0.1
+    return [(m1, 8), (m2, 8), (m3, 8), (m4, 4), (m5, 1), (m6, 3)]
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 @pytest.mark.parametrize("near_only", [True, False])
 def test_d2q9_schedule_solids(case, near_only):
     """Bounce-back in both steps; the mask-free code on chunks with no
