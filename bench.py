@@ -5,8 +5,9 @@ triply periodic Taylor-Green vortex (U0 = 0.05, Re = 1600, Lambda = 1/4),
 inputs resident in HBM, timed with HIP events on the stream the kernels run
 on.  The same JSON line carries the other forms of the metric:
 D3Q19 512^3 with FP32 vs FP16 vs BF16 shifted storage, the batched D2Q9
-form (512 uneven lattices, one graph-replayed launch per step, and the
-one-launch-per-lattice comparison), and the two D2Q9 single-lattice
+form (512 uneven lattices, graph-replayed two-step passes, one step per
+pass with the autotuned tile plan, and the one-launch-per-lattice
+comparison), and the two D2Q9 single-lattice
 configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64),
 the collision-model comparison, D3Q27 (hybrid P-TRT, FP32 / FP16, and
 its comparison models) on the 256^3 vortex, the forcing schemes (Scheme II
@@ -158,10 +159,16 @@ def form_batch(P, torch, stream, steps, warmup):
     b = P.ptrt_batch_create(specs, "f32")
     try:
         P.ptrt_batch_set_stream(b, stream)
+        # tile plan of the one-step launches (odd steps, one step per pass)
         plan = P.ptrt_batch_autotune(b)
         nodes = P.ptrt_batch_nodes(b)
         bps = P.ptrt_batch_bytes_per_step(b)
+        # two steps per pass (the default), then one step per pass
         ms_f, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step(b, k), steps, warmup)
+        spp, pass_bytes = P.ptrt_batch_last_pass(b)
+        P.ptrt_batch_set_steps_per_pass(b, 1)
+        ms_1, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step(b, k), steps, warmup)
+        P.ptrt_batch_set_steps_per_pass(b, 2)
         sep_steps = max(10, steps // 10)
         ms_s, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step_separate(b, k),
                               sep_steps, 2)
@@ -169,6 +176,7 @@ def form_batch(P, torch, stream, steps, warmup):
     finally:
         P.ptrt_batch_destroy(b)
     mf = ms_f / steps
+    m1 = ms_1 / steps
     return {
         "workload": "512 independent D2Q9 P-TRT FP32 lattices (nx, ny in [32, 512], seed 260206686): "
                     "256 force-driven channels + 256 periodic boxes with a square obstacle, per-instance tau+, Lambda=3/16",
@@ -176,7 +184,14 @@ def form_batch(P, torch, stream, steps, warmup):
         "plan": {"tile_x": plan[0], "tile_y": plan[1], "blocks": plan[2], "xcd_order": plan[3]},
         "steps": steps, "ms_per_step": mf,
         "mlups": nodes / (mf * 1e-3) / 1e6, "mflups": fluid / (mf * 1e-3) / 1e6,
+        # one-step accounting (2 Q s + 1 bytes per node per step)
         "achieved_gbs": bps / (mf * 1e-3) / 1e9, "hbm_frac": bps / (mf * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        # the pass actually run: two steps per pass move the bytes of one step
+        "steps_per_pass": spp, "pass_bytes": pass_bytes, "pass_ms": mf * spp,
+        "pass_gbs": pass_bytes / (mf * spp * 1e-3) / 1e9,
+        "one_step_per_pass": {"ms_per_step": m1, "mlups": nodes / (m1 * 1e-3) / 1e6,
+                              "achieved_gbs": bps / (m1 * 1e-3) / 1e9,
+                              "hbm_frac": bps / (m1 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "separate_launches": {"steps": sep_steps, "ms_per_step": ms_s / sep_steps,
                               "mlups": nodes / (ms_s / sep_steps * 1e-3) / 1e6},
         "speedup_vs_separate": (ms_s / sep_steps) / mf,

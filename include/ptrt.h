@@ -305,9 +305,27 @@ int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int x
  * the duration of the call.  Synchronous. */
 int ptrt_batch_autotune(ptrt_batch *b, int *tile_x, int *tile_y, int *blocks, int *xcd_order);
 
-/* Enqueue n steps, each one launch over every instance, replayed from a
- * captured HIP graph.  Asynchronous. */
+/* Enqueue n steps over every instance, replayed from captured HIP graphs
+ * of ten steps: pairs of steps as two-step passes (below), else one launch
+ * per step over every instance with the current tile plan.  Asynchronous. */
 int ptrt_batch_step(ptrt_batch *b, int n);
+
+/* Steps per pass of ptrt_batch_step (1 or 2; default 2).  With 2 and FP32
+ * or FP64 storage, pairs of steps run as passes of the two-step kernel of
+ * ptrt_set_steps_per_pass (first step kept in LDS) over a task table of
+ * (instance, 62-column strip, chunk of rows): one launch for the chunks
+ * with no solid within one row and one for the others (halfway
+ * bounce-back); FP16 / BF16 storage and an odd last step take one step per
+ * pass.  Results are bit-identical either way.  The tile plan (set_plan,
+ * autotune) applies to the one-step launches.  Waits for the batch's
+ * stream. */
+int ptrt_batch_set_steps_per_pass(ptrt_batch *b, int steps);
+
+/* The most recent pass enqueued by ptrt_batch_step: *steps = the steps it
+ * covers (1 or 2; 0 before any) and *bytes = its algorithmic HBM traffic,
+ * (2 Q s + 1) bytes per node for either kind (state read once and written
+ * once, mask bytes).  PTRT_EINVAL on NULL pointers. */
+int ptrt_batch_last_pass(const ptrt_batch *b, int *steps, double *bytes);
 
 /* Enqueue n steps as one launch per instance per step (the comparison
  * baseline for the fused launch).  Asynchronous. */

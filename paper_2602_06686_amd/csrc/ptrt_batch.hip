@@ -10,6 +10,9 @@
 // b, b + G, b + 2G, ... of the table (G = grid size).  Each node runs the
 // same pull() and collide() as the single-lattice kernel, so an instance
 // evolves bit for bit like a single lattice with the same parameters.
+// Two steps per pass (FP32 / FP64): a task table lists (instance, strip,
+// chunk of rows) for the single-lattice two-step pass (step2.hpp); one wave
+// runs one task on its instance's block of the state, mask and constants.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +21,7 @@
 #include <vector>
 
 #include "host_common.hpp"
+#include "step_launch.hpp"
 
 using namespace ptrt;
 
@@ -76,8 +80,34 @@ k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__re
     }
 }
 
+// Two steps per pass: wave task t is tasks[t] = {instance, x0, ys, ye}, a
+// strip of columns x0 ... x0 + BX - 1 and rows ys ... ye - 1 of the
+// instance; MASK as in step2_2d_task (tasks with no solid within one row of
+// rows ys - 1 ... ye run with MASK = false).
+template <class S, bool NT, int NW, bool MASK>
+__global__ void __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(8, 8)))
+k_batch_step2(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+              const BInst<typename Codec<S>::compute> *__restrict__ inst,
+              const int4 *__restrict__ tasks, int ntasks)
+{
+    using SH = Step2Shape2D<S, MASK>;
+    __shared__ S lds_all[NW * SH::K::planes * SH::W];
+    int wg, unused_y, unused_z;
+    xcd_block(wg, unused_y, unused_z);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int t = wg * NW + w;
+    if (t >= ntasks) return;
+    const int4 tk = tasks[t];
+    const BInst<typename Codec<S>::compute> p = inst[tk.x];
+    step2_2d_task<S, NT, MASK>(src + p.off, dst + p.off, mask + p.moff, p.g, p.r,
+                               lds_all + w * (SH::K::planes * SH::W), tk.y, tk.z, tk.w);
+}
+
 thread_local std::string g_batch_create_error = "no error";
-constexpr int GRAPH_STEPS = 10; // even: a replay returns to the same buffer parity
+// steps per captured graph; the buffer parity change of a replay is
+// recorded at capture (odd with two-step passes)
+constexpr int GRAPH_STEPS = 10;
 constexpr int BLK_X = 64, BLK_Y = 4;
 
 struct HostInst {
@@ -106,6 +136,14 @@ struct ptrt_batch {
     double *d_red = nullptr;
     hipStream_t stream = nullptr, capture_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_flip[2] = {0, 0}; // buffer parity change of a replay
+    // two steps per pass: steps per pass asked for, rows per chunk, the
+    // task table (tasks without solids near, then the others), stores
+    int spp = 2, yc2 = 0;
+    int4 *d_tasks2 = nullptr;
+    int n_plain2 = 0, n_masked2 = 0;
+    bool nt = false;
+    int last_steps = 0;
     std::string err = "no error";
 };
 
@@ -207,11 +245,92 @@ void launch_fused(ptrt_batch *b, hipStream_t s)
 
 int launch_fused_any(ptrt_batch *b, hipStream_t s)
 {
+    b->last_steps = 1;
     return dispatch(PTRT_D2Q9, b->storage, false, [&](auto, auto st, auto) -> int {
         using S = typename decltype(st)::type;
         launch_fused<S>(b, s);
         return PTRT_OK;
     });
+}
+
+bool two_step(const ptrt_batch *b) { return b->spp == 2 && b->d_tasks2 != nullptr; }
+
+// One pass of two steps: the tasks without solids near, then the others.
+void launch_pass2_any(ptrt_batch *b, hipStream_t s)
+{
+    b->last_steps = 2;
+    dispatch(PTRT_D2Q9, b->storage, false, [&](auto, auto st, auto) -> int {
+        using S = typename decltype(st)::type;
+        using C = typename Codec<S>::compute;
+        if constexpr (sizeof(S) != 2) { // FP16 / BF16: no task table
+            constexpr int NW = Step2Shape2D<S>::NW;
+            auto go = [&](auto mc, const int4 *list, int n) {
+                constexpr bool M = decltype(mc)::value;
+                if (n == 0) return;
+                const dim3 grid((n + NW - 1) / NW), block(64 * NW);
+                const S *src = (const S *)b->buf[b->cur];
+                S *dst = (S *)b->buf[b->cur ^ 1];
+                if (b->nt)
+                    hipLaunchKernelGGL((k_batch_step2<S, true, NW, M>), grid, block, 0, s, src, dst,
+                                       b->d_mask, (const BInst<C> *)b->d_inst, list, n);
+                else
+                    hipLaunchKernelGGL((k_batch_step2<S, false, NW, M>), grid, block, 0, s, src, dst,
+                                       b->d_mask, (const BInst<C> *)b->d_inst, list, n);
+            };
+            go(std::false_type{}, b->d_tasks2, b->n_plain2);
+            go(std::true_type{}, b->d_tasks2 + b->n_plain2, b->n_masked2);
+        }
+        return PTRT_OK;
+    });
+    b->cur ^= 1;
+}
+
+// n steps on stream s: two-step passes while two steps remain (where
+// allowed), the rest one launch per step.
+void advance(ptrt_batch *b, hipStream_t s, int n)
+{
+    if (two_step(b))
+        for (; n >= 2; n -= 2) launch_pass2_any(b, s);
+    for (; n > 0; --n) launch_fused_any(b, s);
+}
+
+// The two-step task table (FP32 / FP64): per instance, strips of BX
+// columns (the last may be partial) times chunks of yc2 rows (the last may
+// be partial), a chunk taking the masked code when one of its rows ys - 1
+// ... ye has a solid within one row (near, per instance at noff).
+int build_tasks2(ptrt_batch *b, const std::vector<uint8_t> &near)
+{
+    if (b->storage != PTRT_F32 && b->storage != PTRT_F64) return PTRT_OK;
+    constexpr int BX = Step2Shape2D<float>::BX;
+    long long strip_rows = 0;
+    for (const HostInst &h : b->inst) strip_rows += (long long)((h.nx + BX - 1) / BX) * h.ny;
+    // the single-lattice rule, at most 3 rows: on the 512-lattice benchmark
+    // batch (38M nodes) 3 rows measured best, FP32 and FP64, with or
+    // without solids (FP32 GLUPS for 1, 2, 3, 4, 5, 7, 9, 12 rows: 92.5,
+    // 85.9, 95.0, 92.5, 93.1, 90.1, 86.4, 83.3; one step per pass 81.1)
+    b->yc2 = std::min(3, step2_2d_rows_for(b->storage, strip_rows, b->total_nodes));
+    std::vector<int4> plain, masked;
+    for (int k = 0; k < b->count; ++k) {
+        const HostInst &h = b->inst[k];
+        const int strips = (h.nx + BX - 1) / BX;
+        for (int ys = 0; ys < h.ny; ys += b->yc2) {
+            const int ye = std::min(ys + b->yc2, h.ny);
+            bool nr = false;
+            for (int y = ys - 1; y <= ye && !nr; ++y)
+                nr = near[(size_t)(h.noff + ((y % h.ny) + h.ny) % h.ny)] != 0;
+            for (int bx = 0; bx < strips; ++bx)
+                (nr ? masked : plain).push_back(make_int4(k, bx * BX, ys, ye));
+        }
+    }
+    b->n_plain2 = (int)plain.size();
+    b->n_masked2 = (int)masked.size();
+    plain.insert(plain.end(), masked.begin(), masked.end());
+    BHIPCHK(b, hipMalloc(&b->d_tasks2, sizeof(int4) * plain.size()));
+    BHIPCHK(b, hipMemcpy(b->d_tasks2, plain.data(), sizeof(int4) * plain.size(), hipMemcpyHostToDevice));
+    // non-temporal stores once the two state buffers exceed the 256 MB
+    // last-level cache (as for a single lattice)
+    b->nt = 2.0 * (double)b->total_elems * (double)storage_bytes(b->storage) > 256.0 * 1024 * 1024;
+    return PTRT_OK;
 }
 
 int capture_graph(ptrt_batch *b, int parity)
@@ -220,8 +339,9 @@ int capture_graph(ptrt_batch *b, int parity)
     b->cur = parity;
     hipGraph_t g = nullptr;
     BHIPCHK(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < GRAPH_STEPS; ++k) launch_fused_any(b, b->capture_stream);
+    advance(b, b->capture_stream, GRAPH_STEPS);
     hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
+    b->graph_flip[parity] = b->cur ^ parity;
     b->cur = saved;
     if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph[parity], g, nullptr, nullptr, 0);
@@ -349,6 +469,7 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
     if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(PTRT_EDEVICE, "capture stream");
     if (build_tiles(b) != PTRT_OK) return cleanup(PTRT_EDEVICE, b->err);
+    if (build_tasks2(b, near) != PTRT_OK) return cleanup(PTRT_EDEVICE, b->err);
     for (int k = 0; k < count; ++k) {
         rc = ptrt_batch_init_equilibrium(b, k, nullptr, nullptr);
         if (rc != PTRT_OK) return cleanup(rc, b->err);
@@ -420,10 +541,30 @@ int ptrt_batch_step(ptrt_batch *b, int n)
             if (rc != PTRT_OK) return rc;
         }
         BHIPCHK(b, hipGraphLaunch(b->graph[b->cur], b->stream));
+        b->last_steps = two_step(b) ? 2 : 1;
+        b->cur ^= b->graph_flip[b->cur];
         n -= GRAPH_STEPS;
     }
-    for (; n > 0; --n) launch_fused_any(b, b->stream);
+    advance(b, b->stream, n);
     BHIPCHK(b, hipGetLastError());
+    return PTRT_OK;
+}
+
+int ptrt_batch_set_steps_per_pass(ptrt_batch *b, int steps)
+{
+    if (!b) return PTRT_EINVAL;
+    if (steps != 1 && steps != 2) return bfail(b, PTRT_EINVAL, "steps per pass must be 1 or 2");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->spp = steps;
+    drop_graphs(b);
+    return PTRT_OK;
+}
+
+int ptrt_batch_last_pass(const ptrt_batch *b, int *steps, double *bytes)
+{
+    if (!b || !steps || !bytes) return PTRT_EINVAL;
+    *steps = b->last_steps;
+    *bytes = b->last_steps ? ptrt_batch_bytes_per_step(b) : 0.0;
     return PTRT_OK;
 }
 
@@ -621,6 +762,7 @@ int ptrt_batch_destroy(ptrt_batch *b)
     if (b->d_near) hipFree(b->d_near);
     if (b->d_inst) hipFree(b->d_inst);
     if (b->d_tiles) hipFree(b->d_tiles);
+    if (b->d_tasks2) hipFree(b->d_tasks2);
     if (b->d_partials) hipFree(b->d_partials);
     if (b->d_red) hipFree(b->d_red);
     if (b->capture_stream) hipStreamDestroy(b->capture_stream);

@@ -265,41 +265,26 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Task t of the launch is (strip, chunk) = tasks[t] % strips, tasks[t] /
-// strips, or t itself without a list.  MASK: the tasks read the mask
-// (halfway bounce-back; tasks whose rows ys - 1 ... ye hold no solid within
-// one row run the MASK = false kernel): the first step pulls the node's own
-// opposite population where the source is solid, the second step likewise
-// from the first step's values of its own node, and solid second-step
-// nodes are not stored (as in the one-step kernel).
-// (eight waves per SIMD: FP32 fits in 64 VGPRs; measured +1.5 % at 4096^2)
-template <class S, bool NT, int NW, bool MASK>
-__global__ void __launch_bounds__(64 * NW)
-__attribute__((amdgpu_waves_per_eu(8, 8)))
-k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
-           const int *__restrict__ task_list, Geom g, Coef<D2Q9, typename Codec<S>::compute> r,
-           int yc, int strips, int tasks)
+// One task of the two-step pass, run by one wave: second steps for rows ys
+// ... ye - 1 (ye > ys) of the strip of columns x0 ... x0 + BX - 1 (those
+// inside the lattice), first steps kept in the wave's K::planes rows of W
+// values at lds.  MASK: the task reads the mask (halfway bounce-back; a
+// task whose rows ys - 1 ... ye hold no solid within one row may run with
+// MASK = false): the first step pulls the node's own opposite population
+// where the source is solid, the second step likewise from the first
+// step's values of its own node, and solid second-step nodes are not
+// stored (as in the one-step kernel).
+template <class S, bool NT, bool MASK>
+__device__ __forceinline__ void
+step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+              const Geom &g, const Coef<D2Q9, typename Codec<S>::compute> &r, S *lds, int x0,
+              int ys, int ye)
 {
     using L = D2Q9;
     using C = typename Codec<S>::compute;
     using SH = Step2Shape2D<S, MASK>;
     using K = typename SH::K;
     constexpr int W = SH::W, BX = SH::BX;
-    __shared__ S lds_all[NW * K::planes * W];
-
-    // the NW waves of a workgroup run independent tasks (strip, chunk),
-    // neighbouring strips of one chunk
-    int wg, unused_y, unused_z;
-    xcd_block(wg, unused_y, unused_z);
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int t = wg * NW + w;
-    if (t >= tasks) return;
-    const int task = task_list ? task_list[t] : t;
-    S *lds = lds_all + w * (K::planes * W);
-    const int bx = task % strips, by = task / strips;
-    const int x0 = bx * BX;
-    const int ys = by * yc;
-    const int ye = min(ys + yc, g.ny);
     const int lane = (int)(threadIdx.x & 63);
     auto wrapc = [](int v, int n) {
         v %= n;
@@ -444,6 +429,32 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__rest
         row_step(it + 1, raw1);
     }
     if (nb & 1) row_step(it, raw0);
+}
+
+// Task t of the launch is (strip, chunk) = tasks[t] % strips, tasks[t] /
+// strips, or t itself without a list; chunks of yc rows, the last partial.
+// The NW waves of a workgroup run independent tasks (neighbouring strips of
+// one chunk).  Eight waves per SIMD: FP32 fits in 64 VGPRs (measured
+// +1.5 % at 4096^2).
+template <class S, bool NT, int NW, bool MASK>
+__global__ void __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(8, 8)))
+k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+           const int *__restrict__ task_list, Geom g, Coef<D2Q9, typename Codec<S>::compute> r,
+           int yc, int strips, int tasks)
+{
+    using SH = Step2Shape2D<S, MASK>;
+    __shared__ S lds_all[NW * SH::K::planes * SH::W];
+    int wg, unused_y, unused_z;
+    xcd_block(wg, unused_y, unused_z);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int t = wg * NW + w;
+    if (t >= tasks) return;
+    const int task = task_list ? task_list[t] : t;
+    const int bx = task % strips, by = task / strips;
+    const int ys = by * yc;
+    step2_2d_task<S, NT, MASK>(src, dst, mask, g, r, lds_all + w * (SH::K::planes * SH::W),
+                               bx * SH::BX, ys, min(ys + yc, g.ny));
 }
 
 } // namespace ptrt

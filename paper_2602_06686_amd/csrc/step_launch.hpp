@@ -52,14 +52,21 @@ bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes);
 // per CU as LDS allows), at most 9 rows (7 from 2^22 nodes on, 2 - 3 %
 // faster there), and never 4 or 8, which measured 5 - 15 % slower than 5
 // and 9 at 724^2 - 1024^2.
+// strip_rows: strips x rows summed over the lattices of the launch, nodes:
+// their nodes.
+inline int step2_2d_rows_for(int storage, long long strip_rows, long long nodes)
+{
+    const long long target = storage == PTRT_F64 ? 800 : 1600;
+    const long long cap = nodes >= (1LL << 22) ? 7 : 9;
+    long long yc = std::min(cap, std::max(1LL, (strip_rows + target - 1) / target));
+    if (yc == 4 || yc == 8) ++yc;
+    return (int)yc;
+}
+
 inline int step2_2d_rows(int storage, int nx, int ny)
 {
     const long long strips = (nx + Step2Shape2D<float>::BX - 1) / Step2Shape2D<float>::BX;
-    const long long target = storage == PTRT_F64 ? 800 : 1600;
-    const long long cap = (long long)nx * ny >= (1LL << 22) ? 7 : 9;
-    long long yc = std::min(cap, std::max(1LL, (strips * ny + target - 1) / target));
-    if (yc == 4 || yc == 8) ++yc;
-    return (int)yc;
+    return step2_2d_rows_for(storage, strips * ny, (long long)nx * ny);
 }
 
 template <class L>

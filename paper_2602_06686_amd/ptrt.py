@@ -86,6 +86,8 @@ _SIGS = {
                                            ctypes.c_int]),
     "ptrt_batch_autotune": (ctypes.c_int, [_vp, _ip, _ip, _ip, _ip]),
     "ptrt_batch_step": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_batch_set_steps_per_pass": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_batch_last_pass": (ctypes.c_int, [_vp, _ip, _dp]),
     "ptrt_batch_step_separate": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_batch_moments": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "ptrt_batch_get_populations": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
@@ -408,6 +410,18 @@ def ptrt_batch_autotune(b):
 
 def ptrt_batch_step(b, n=1):
     return _check(_lib.ptrt_batch_step(b.ptr, int(n)), b.ptr, True)
+
+
+def ptrt_batch_set_steps_per_pass(b, steps):
+    return _check(_lib.ptrt_batch_set_steps_per_pass(b.ptr, int(steps)), b.ptr, True)
+
+
+def ptrt_batch_last_pass(b):
+    """(steps covered, algorithmic HBM bytes) of the most recent pass."""
+    steps = ctypes.c_int()
+    nbytes = ctypes.c_double()
+    _check(_lib.ptrt_batch_last_pass(b.ptr, ctypes.byref(steps), ctypes.byref(nbytes)), b.ptr, True)
+    return steps.value, nbytes.value
 
 
 def ptrt_batch_step_separate(b, n=1):

@@ -154,3 +154,64 @@ def test_full_batch_sampled_instances_vs_oracle():
             assert err <= 1e-5 * scale + 1e-9, (k, err, scale)
     finally:
         P.ptrt_batch_destroy(b)
+
+
+def _batch_run(specs, storage, spp, schedule, seed0=300):
+    """Populations of every instance after the step counts in schedule
+    (calls of ptrt_batch_step), with spp steps per pass."""
+    b = P.ptrt_batch_create(specs, storage)
+    try:
+        P.ptrt_batch_set_steps_per_pass(b, spp)
+        for k, s in enumerate(specs):
+            P.ptrt_batch_init_equilibrium(b, k, *_init_fields(s, seed0 + k))
+        for n in schedule:
+            P.ptrt_batch_step(b, n)
+        return [P.ptrt_batch_get_populations(b, k) for k in range(len(specs))], P.ptrt_batch_last_pass(b)
+    finally:
+        P.ptrt_batch_destroy(b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("schedule", [[1], [2], [7], [13], [10, 10, 3], [25, 1, 14]])
+def test_batch_two_steps_per_pass_bitwise(storage, schedule):
+    """Two steps per pass (task table of strips and one-row chunks; channels,
+    obstacles and a solid-free instance, widths 5 ... 257) against one step
+    per pass: bit for bit, through graph replays (odd parity change) and odd
+    remainders."""
+    print_case("batch steps per pass 2 vs 1", storage, schedule)
+    specs = _small_specs(seed=3)
+    a, pa = _batch_run(specs, storage, 1, schedule)
+    c, pc = _batch_run(specs, storage, 2, schedule)
+    for k, s in enumerate(specs):
+        fluid = np.broadcast_to(True if s["mask"] is None else s["mask"] == 0, a[k].shape)
+        assert np.array_equal(a[k][fluid], c[k][fluid]), f"instance {k}"
+    # the last call: graphs of ten steps, then pairs, then an odd step
+    assert pa[0] == 1
+    assert pc[0] == (2 if schedule[-1] % 10 % 2 == 0 else 1)
+    assert pc[1] == pa[1] > 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_two_steps_per_pass_larger_chunks_bitwise(storage):
+    """48 lattices of the benchmark's kinds and sizes (chunks of several
+    rows, partial strips and chunks, masked and mask-free tasks): two steps
+    per pass against one, bit for bit."""
+    print_case("batch 48 lattices steps per pass 2 vs 1", storage)
+    specs = I.batch_specs(count=48, seed=5)
+    a, _ = _batch_run(specs, storage, 1, [12, 3])
+    c, pc = _batch_run(specs, storage, 2, [12, 3])
+    assert pc[0] == 1
+    for k in range(len(specs)):
+        fluid = np.broadcast_to(specs[k]["mask"] == 0, a[k].shape)
+        assert np.array_equal(a[k][fluid], c[k][fluid]), f"instance {k}"
+
+
+def test_batch_two_steps_per_pass_half_precision_falls_back():
+    print_case("batch steps per pass 2, FP16 / BF16: one step per pass")
+    specs = _small_specs(seed=4)[:3]
+    for st in ("f16", "bf16"):
+        a, _ = _batch_run(specs, st, 1, [6])
+        c, pc = _batch_run(specs, st, 2, [6])
+        assert pc[0] == 1
+        for k in range(len(specs)):
+            assert np.array_equal(a[k], c[k])
