@@ -431,16 +431,16 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
     if (nb & 1) row_step(it, raw0);
 }
 
-// Task t of the launch is (strip, chunk) = tasks[t] % strips, tasks[t] /
-// strips, or t itself without a list; chunks of yc rows, the last partial.
-// The NW waves of a workgroup run independent tasks (neighbouring strips of
-// one chunk).  Eight waves per SIMD: FP32 fits in 64 VGPRs (measured
-// +1.5 % at 4096^2).
+// Task t of the launch: task_list[t] = {unused, x0, ys, ye}, or without a
+// list (strip, chunk) = (t % strips, t / strips) with chunks of yc rows,
+// the last partial.  The NW waves of a workgroup run independent tasks
+// (neighbouring strips of one chunk).  Eight waves per SIMD: FP32 fits in
+// 64 VGPRs (measured +1.5 % at 4096^2).
 template <class S, bool NT, int NW, bool MASK>
 __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
-           const int *__restrict__ task_list, Geom g, Coef<D2Q9, typename Codec<S>::compute> r,
+           const int4 *__restrict__ task_list, Geom g, Coef<D2Q9, typename Codec<S>::compute> r,
            int yc, int strips, int tasks)
 {
     using SH = Step2Shape2D<S, MASK>;
@@ -450,11 +450,20 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__rest
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int t = wg * NW + w;
     if (t >= tasks) return;
-    const int task = task_list ? task_list[t] : t;
-    const int bx = task % strips, by = task / strips;
-    const int ys = by * yc;
-    step2_2d_task<S, NT, MASK>(src, dst, mask, g, r, lds_all + w * (SH::K::planes * SH::W),
-                               bx * SH::BX, ys, min(ys + yc, g.ny));
+    int x0, ys, ye;
+    if (task_list) {
+        const int4 tk = task_list[t];
+        x0 = tk.y;
+        ys = tk.z;
+        ye = tk.w;
+    } else {
+        const int bx = t % strips, by = t / strips;
+        x0 = bx * SH::BX;
+        ys = by * yc;
+        ye = min(ys + yc, g.ny);
+    }
+    step2_2d_task<S, NT, MASK>(src, dst, mask, g, r, lds_all + w * (SH::K::planes * SH::W), x0,
+                               ys, ye);
 }
 
 } // namespace ptrt

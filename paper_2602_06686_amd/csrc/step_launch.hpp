@@ -26,10 +26,12 @@ struct StepLaunch {
     void *phi = nullptr; // Phi field in the compute type (FORCE_II_G)
     bool open = false;   // D2Q9 inlet / outlet in x (values in g)
     hipStream_t stream = nullptr;
-    // D2Q9 with solids, two steps per pass: the (strip, chunk) tasks without
-    // and with a solid within one row of their rows (Step2Shape2D)
-    const int *tasks_plain = nullptr, *tasks_masked = nullptr;
+    // D2Q9 with solids, two steps per pass: the tasks {unused, x0, ys, ye}
+    // without and with a solid within one row of their rows, and the rows
+    // the latter cover
+    const int4 *tasks_plain = nullptr, *tasks_masked = nullptr;
     int n_plain = 0, n_masked = 0;
+    long long masked_rows = 0;
 };
 
 void launch_step_d2q9(const StepLaunch &a);
@@ -53,10 +55,10 @@ bool launch_step2_d3q27(const StepLaunch &a, double *pass_bytes);
 // faster there), and never 4 or 8, which measured 5 - 15 % slower than 5
 // and 9 at 724^2 - 1024^2.
 // strip_rows: strips x rows summed over the lattices of the launch, nodes:
-// their nodes.
-inline int step2_2d_rows_for(int storage, long long strip_rows, long long nodes)
+// their nodes; scale multiplies the task target.
+inline int step2_2d_rows_for(int storage, long long strip_rows, long long nodes, int scale = 1)
 {
-    const long long target = storage == PTRT_F64 ? 800 : 1600;
+    const long long target = (storage == PTRT_F64 ? 800 : 1600) * (long long)scale;
     const long long cap = nodes >= (1LL << 22) ? 7 : 9;
     long long yc = std::min(cap, std::max(1LL, (strip_rows + target - 1) / target));
     if (yc == 4 || yc == 8) ++yc;
@@ -78,17 +80,17 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
         // and FP64 (64^2 ... 4096^2, 8 - 30 %); none in FP16 / BF16, whose
         // one-step kernel moves half the bytes for the same arithmetic
         if (a.storage == PTRT_F16 || a.storage == PTRT_BF16) return false;
-        // with solids: the tasks near solids take the masked kernel, a
-        // second launch slower per node than one step per pass, so the pass
-        // is used in FP64 while they are at most 30 % of the tasks
-        // (measured, one step -> two: channel 4096^2 42.3 -> 61.4 GLUPS,
-        // 2048^2 40.6 -> 50.8; an obstacle over 1/8 of the rows 42.7 ->
-        // 61.1); in FP32 it gained 10 % at 4096^2 and lost 3 % at 2048^2
+        // with solids: the rows near solids take the masked kernel in a
+        // second launch, slower per node than one step per pass, so the
+        // pass is used from 2^20 nodes on while they are at most 30 % of
+        // the rows (measured, one step -> two, GLUPS: FP32 channel 1024^2
+        // 75.4 -> 89.0, 2048^2 81.8 -> 100.7, 4096^2 86.1 -> 102.2, an
+        // obstacle over 1/8 of the rows 4096^2 85.8 -> 101.1; FP64 channel
+        // 1024^2 41.8 -> 58.3, 4096^2 42.2 -> 64.0; at 512^2 both lost 10 %)
         if (a.has_mask) {
-            const int all = a.n_plain + a.n_masked;
-            if (a.storage != PTRT_F64 || all == 0 || !a.tasks_plain || !a.tasks_masked)
-                return false;
-            if (a.n_masked > 0.3 * all) return false;
+            if ((long long)a.g.nx * a.g.ny < (1LL << 20)) return false;
+            if (!a.tasks_plain || !a.tasks_masked || a.n_plain + a.n_masked == 0) return false;
+            if (a.masked_rows > 0.3 * a.g.ny) return false;
         }
         dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
             using S = typename decltype(st)::type;
@@ -107,7 +109,7 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                     *pass_bytes = (2.0 * L::Q * sizeof(S) + (a.has_mask ? 1.0 : 0.0)) *
                                   a.g.nx * a.g.ny;
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
-                auto go = [&](auto mc, const int *list, int n) {
+                auto go = [&](auto mc, const int4 *list, int n) {
                     constexpr bool M = decltype(mc)::value;
                     if (n == 0) return;
                     const dim3 grid((n + NW - 1) / NW, 1, 1);
@@ -121,10 +123,8 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                                            list, a.g, r, yc, strips, n);
                 };
                 if (a.has_mask) {
-                    if constexpr (sizeof(S) == 8) {
-                        go(std::false_type{}, a.tasks_plain, a.n_plain);
-                        go(std::true_type{}, a.tasks_masked, a.n_masked);
-                    }
+                    go(std::false_type{}, a.tasks_plain, a.n_plain);
+                    go(std::true_type{}, a.tasks_masked, a.n_masked);
                 } else {
                     go(std::false_type{}, nullptr, tasks);
                 }

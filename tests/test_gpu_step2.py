@@ -85,8 +85,8 @@ def _last_pass(shape, storage, mask=None):
 
 def test_two_steps_per_pass_d2q9_used_where_it_pays():
     """The pass covers two steps at every size in FP32 and FP64 only, with
-    or without a body force; with solids in FP64 while few rows are near
-    them."""
+    or without a body force; with solids from 2^20 nodes on while few rows
+    are near them."""
     print_case("D2Q9 last pass: sizes, storage types, force, solids")
     assert _last_pass((1, 512, 1024), "f32") == (2, 2.0 * 1024 * 512 * 9 * 4)
     assert _last_pass((1, 3, 5), "f32") == (2, 2.0 * 5 * 3 * 9 * 4)
@@ -95,58 +95,60 @@ def test_two_steps_per_pass_d2q9_used_where_it_pays():
     for st in ("f16", "bf16"):
         assert _last_pass((1, 1024, 1024), st)[0] == 1
         assert _last_pass((1, 64, 64), st)[0] == 1
-    mask = np.zeros((1, 512, 1024), dtype=np.uint8)
+    mask = np.zeros((1, 1024, 1024), dtype=np.uint8)
     mask[0, 0, :] = 1
-    # with solids, FP64 only: the state and the mask bytes
-    assert _last_pass((1, 512, 1024), "f64", mask=mask) == (2, (2.0 * 9 * 8 + 1) * 1024 * 512)
-    assert _last_pass((1, 512, 1024), "f32", mask=mask)[0] == 1
+    # with solids: the state and the mask bytes
+    assert _last_pass((1, 1024, 1024), "f64", mask=mask) == (2, (2.0 * 9 * 8 + 1) * 1024 * 1024)
+    assert _last_pass((1, 1024, 1024), "f32", mask=mask) == (2, (2.0 * 9 * 4 + 1) * 1024 * 1024)
+    assert _last_pass((1, 1024, 1024), "f16", mask=mask)[0] == 1
+    # below 2^20 nodes with solids: one step per pass
+    assert _last_pass((1, 1023, 1024), "f64", mask=mask[:, :1023])[0] == 1
+    assert _last_pass((1, 64, 64), "f32", mask=mask[:, :64, :64])[0] == 1
     for m in _d2_masks():
-        assert _last_pass(m.shape, "f64", mask=m)[0] == 2
+        for st in ("f32", "f64"):
+            assert _last_pass(m.shape, st, mask=m)[0] == 2
     # solids near most rows: one step per pass
-    dense = (np.random.default_rng(4).random((1, 512, 1024)) < 0.01).astype(np.uint8)
-    assert _last_pass((1, 512, 1024), "f64", mask=dense)[0] == 1
+    dense = (np.random.default_rng(4).random((1, 1024, 1024)) < 0.01).astype(np.uint8)
+    assert _last_pass((1, 1024, 1024), "f64", mask=dense)[0] == 1
     f = [2e-5, -1e-5, 0]
     shape = (1, 600, 1000)
     assert np.array_equal(_run(0, shape, "f32", 9, 1, force=f), _run(0, shape, "f32", 9, 2, force=f))
 
 
 def _d2_masks():
-    """Solid layouts with few rows near solids (where two steps per pass are
-    used): channel walls on the periodic y seam, a band of random solids
-    (some next to each other, across chunk and strip borders), a square
-    obstacle, and a solid column on the periodic x seam with blocks at a
-    strip border and in the last, partial strip; then small lattices."""
+    """Solid layouts of at least 2^20 nodes with few rows near solids (where
+    two steps per pass are used): channel walls on the periodic y seam, a
+    band of random solids (some next to each other, across chunk and strip
+    borders), a square obstacle, a solid column on the periodic x seam with
+    blocks at a strip border and in the last, partial strip, and a tall
+    block (masked rows in chunks of several rows)."""
     rng = np.random.default_rng(21)
     out = []
-    m = np.zeros((1, 600, 1000), dtype=np.uint8)
+    m = np.zeros((1, 1050, 1000), dtype=np.uint8)
     m[0, 0, :] = m[0, -1, :] = 1
     out.append(m)
-    m = np.zeros((1, 515, 520), dtype=np.uint8)
-    m[0, 100:141, :] = rng.random((41, 520)) < 0.05
+    m = np.zeros((1, 1030, 1030), dtype=np.uint8)
+    m[0, 200:241, :] = rng.random((41, 1030)) < 0.05
     out.append(m)
-    m = np.zeros((1, 1030, 520), dtype=np.uint8)
-    m[0, 500:533, 240:273] = 1
+    m = np.zeros((1, 2060, 520), dtype=np.uint8)
+    m[0, 1000:1033, 240:273] = 1
     out.append(m)
-    m = np.zeros((1, 700, 801), dtype=np.uint8)
+    m = np.zeros((1, 1400, 801), dtype=np.uint8)
     m[0, 300:321, 0] = 1
     m[0, 300:310, 700:800] = 1
     m[0, 7:9, 61:63] = 1
     out.append(m)
-    # small lattices (chunks of 1 and 3 rows): channel walls, a random band
-    m = np.zeros((1, 64, 64), dtype=np.uint8)
-    m[0, 0, :] = m[0, -1, :] = 1
-    out.append(m)
-    m = np.zeros((1, 301, 390), dtype=np.uint8)
-    m[0, 150:170, :] = rng.random((20, 390)) < 0.1
+    m = np.zeros((1, 1100, 1000), dtype=np.uint8)
+    m[0, 100:301, 400:600] = 1
     out.append(m)
     return out
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(5))
 @pytest.mark.parametrize("steps", [2, 7, 40])
-def test_two_steps_per_pass_d2q9_solids_bitwise(case, steps):
-    """With solids the pass covers two steps in FP64 (below)."""
-    storage, mask = "f64", _d2_masks()[case]
+def test_two_steps_per_pass_d2q9_solids_bitwise(storage, case, steps):
+    mask = _d2_masks()[case]
     print_case("D2Q9 with solids, steps per pass 2 vs 1", storage, mask.shape, steps)
     a = _run(0, mask.shape, storage, steps, 1, mask=mask, force=[1e-6, 0, 0])
     b = _run(0, mask.shape, storage, steps, 2, mask=mask, force=[1e-6, 0, 0])
@@ -155,11 +157,11 @@ def test_two_steps_per_pass_d2q9_solids_bitwise(case, steps):
 
 
 def test_two_steps_per_pass_d2q9_channel_matches_oracle():
-    print_case("D2Q9 channel, steps per pass 2, FP64 520x510 vs oracle, 40 steps")
-    nz, ny, nx = n = (1, 510, 520)
+    print_case("D2Q9 channel, steps per pass 2, FP64 1020x1030 vs oracle, 40 steps")
+    nz, ny, nx = n = (1, 1030, 1020)
     mask = np.zeros(n, dtype=np.uint8)
     mask[0, 0, :] = mask[0, -1, :] = 1
-    mask[0, 200:220, 100:130] = 1
+    mask[0, 400:420, 100:130] = 1
     rng = np.random.default_rng(17)
     rho, u = I.random_fields(rng, n, umax=0.03)
     u = u[:2]

@@ -2,7 +2,8 @@
 the CPU: which first-step value each second-step population reads, in
 which LDS slot of its direction class it is held, which halo a workgroup
 recomputes, and (D2Q9 with solids) where halfway bounce-back takes the
-node's own first-step value instead.  The schedule is emulated here in
+node's own first-step value instead, on the host's split into mask-free
+chunks and shorter masked ones.  The schedule is emulated here in
 NumPy with the oracle's collision as the per-node map, and the second
 step's pulled populations must equal the oracle's state after two steps
 (pulled = pre-collision) exactly.  CPU only: the kernels themselves are
@@ -105,19 +106,32 @@ def test_d3q19_schedule(nx, ny, nz, BY, zc):
     assert np.abs(got - ref).max() < 1e-14
 
 
-def _two_step_2d(stored, e, opp, tp, lam, yc, solid=None, near_only=True):
-    """k_step2_2d schedule on D2Q9: one wave per strip of 62 columns (64 A
-    nodes), chunks of yc rows; with solids, bounce-back in both steps."""
+def _tasks_2d(ny, nx, yc, near=None, ym=None):
+    """(x0, ys, ye, masked) tasks as the host builds them: strips of 62
+    columns times chunks of yc rows; with solids, a chunk with a solid
+    within one row of its rows ys - 1 ... ye is masked and its rows are
+    split into chunks of ym rows (the last partial)."""
+    out = []
+    for ys in range(0, ny, yc):
+        ye = min(ys + yc, ny)
+        masked = near is not None and any(near[y % ny] for y in range(ys - 1, ye + 1))
+        parts = [(y, min(y + ym, ye)) for y in range(ys, ye, ym)] if masked else [(ys, ye)]
+        for a, b in parts:
+            for x0 in range(0, nx, 62):
+                out.append((x0, a, b, masked))
+    return out
+
+
+def _two_step_2d(stored, e, opp, tp, lam, tasks, solid=None):
+    """k_step2_2d schedule on D2Q9: one wave per task (a strip of 62
+    columns, 64 A nodes, and rows ys ... ye - 1); masked tasks apply
+    bounce-back in both steps."""
     Q, _, ny, nx = stored.shape
     st = stored[:, 0]
     W, BX = 64, 62
     bb = solid is not None
     cls, slots, count, index, region, planes = _classes(e, 1, bb)
-    ex, ey = e[:, 0].astype(int), e[:, 1].astype(int)
     m = solid[0] if bb else np.zeros((ny, nx), bool)
-    solid_row = m.any(axis=1)
-    near = np.array([solid_row[(y - 1) % ny] or solid_row[y] or solid_row[(y + 1) % ny]
-                     for y in range(ny)])
     out = np.full((Q, ny, nx), np.nan)
     lanes = np.arange(W)
 
@@ -126,42 +140,39 @@ def _two_step_2d(stored, e, opp, tp, lam, yc, solid=None, near_only=True):
         assert np.all((v >= 0) & (v < planes * W))
         return v
 
-    for by in range((ny + yc - 1) // yc):
-        for bx in range((nx + BX - 1) // BX):
-            x0, ys = bx * BX, by * yc
-            ye = min(ys + yc, ny)
-            masked = bb and (not near_only or any(near[y % ny] for y in range(ys - 1, ye + 1)))
-            ax = (x0 - 1 + lanes) % nx
-            lds = np.full(planes * W, np.nan)
-            for it, k in enumerate(range(ys - 1, ye + 1)):
-                raw = np.empty((Q, W))
-                for i in range(Q):
-                    sy, sx = (k - ey[i]) % ny, (ax - ex[i]) % nx
-                    v = st[i, sy, sx].copy()
-                    if masked and i:
-                        s = m[sy, sx] != 0
-                        v[s] = st[opp[i], k % ny, ax][s]
-                    raw[i] = v
-                post = _collide(O.D2Q9, raw, tp, lam)
-                for i in range(Q):
-                    lds[at(cls[i], index[i], it % slots[cls[i]], lanes)] = post[i]
-                if k < ys + 1:
-                    continue
-                bl = np.arange(1, BX + 1)
-                bl = bl[x0 - 1 + bl < nx]
-                xb = ax[bl]
-                h = np.empty((Q, len(bl)))
-                for i in range(Q):
-                    c = cls[i]
-                    v = lds[at(c, index[i], (it - c) % slots[c], bl - ex[i])].copy()
-                    if masked and i:
-                        s = m[(k - 1 - ey[i]) % ny, (xb - ex[i]) % nx] != 0
-                        io = opp[i]
-                        v[s] = lds[at(cls[io], index[io], (it - 1) % slots[cls[io]], bl)][s]
-                    h[i] = v
-                if masked:
-                    h[:, m[(k - 1) % ny, xb] != 0] = np.nan
-                out[:, (k - 1) % ny, xb] = h
+    for x0, ys, ye, masked in tasks:
+        assert not masked or bb
+        ax = (x0 - 1 + lanes) % nx
+        lds = np.full(planes * W, np.nan)
+        for it, k in enumerate(range(ys - 1, ye + 1)):
+            raw = np.empty((Q, W))
+            for i in range(Q):
+                sy, sx = (k - int(e[i, 1])) % ny, (ax - int(e[i, 0])) % nx
+                v = st[i, sy, sx].copy()
+                if masked and i:
+                    s = m[sy, sx] != 0
+                    v[s] = st[opp[i], k % ny, ax][s]
+                raw[i] = v
+            post = _collide(O.D2Q9, raw, tp, lam)
+            for i in range(Q):
+                lds[at(cls[i], index[i], it % slots[cls[i]], lanes)] = post[i]
+            if k < ys + 1:
+                continue
+            bl = np.arange(1, BX + 1)
+            bl = bl[x0 - 1 + bl < nx]
+            xb = ax[bl]
+            h = np.empty((Q, len(bl)))
+            for i in range(Q):
+                c = cls[i]
+                v = lds[at(c, index[i], (it - c) % slots[c], bl - int(e[i, 0]))].copy()
+                if masked and i:
+                    s = m[(k - 1 - int(e[i, 1])) % ny, (xb - int(e[i, 0])) % nx] != 0
+                    io = opp[i]
+                    v[s] = lds[at(cls[io], index[io], (it - 1) % slots[cls[io]], bl)][s]
+                h[i] = v
+            if masked:
+                h[:, m[(k - 1) % ny, xb] != 0] = np.nan
+            out[:, (k - 1) % ny, xb] = h
     return out
 
 
@@ -171,7 +182,7 @@ def _two_step_2d(stored, e, opp, tp, lam, yc, solid=None, near_only=True):
 def test_d2q9_schedule(ny, nx, yc):
     e, _, opp = O.lattice(O.D2Q9)
     stored, ref = _start(O.D2Q9, (1, ny, nx), 0.7, 0.25)
-    got = _two_step_2d(stored, e, opp, 0.7, 0.25, yc)
+    got = _two_step_2d(stored, e, opp, 0.7, 0.25, _tasks_2d(ny, nx, yc))
     assert not np.isnan(got).any()
     assert np.abs(got - ref[:, 0]).max() < 1e-14
 
@@ -189,19 +200,30 @@ def _masks():
     m5[0] = m5[-1] = 1
     m6 = np.zeros((25, 70), np.uint8)
     m6[10:14] = rng.random((4, 70)) < 0.1
-    return [(m1, 8), (m2, 8), (m3, 8), (m4, 4), (m5, 1), (m6, 3)]
+    # (mask, rows per chunk, rows per masked chunk)
+    return [(m1, 8, 1), (m2, 8, 3), (m3, 8, 2), (m4, 4, 1), (m5, 1, 1), (m6, 3, 2), (m1, 7, 5)]
 
 
-@pytest.mark.parametrize("case", range(6))
-@pytest.mark.parametrize("near_only", [True, False])
-def test_d2q9_schedule_solids(case, near_only):
-    """Bounce-back in both steps; the mask-free code on chunks with no
-    solid within one row (near_only) changes nothing."""
-    mask, yc = _masks()[case]
+def _near_rows(m):
+    ny = m.shape[0]
+    r = m.any(axis=1)
+    return [bool(r[(y - 1) % ny] or r[y] or r[(y + 1) % ny]) for y in range(ny)]
+
+
+@pytest.mark.parametrize("case", range(7))
+@pytest.mark.parametrize("masked_everywhere", [False, True])
+def test_d2q9_schedule_solids(case, masked_everywhere):
+    """Bounce-back in both steps on the masked tasks, whose rows are split
+    into shorter chunks; the mask-free code on chunks with no solid within
+    one row changes nothing (against every task masked)."""
+    mask, yc, ym = _masks()[case]
     ny, nx = mask.shape
     e, _, opp = O.lattice(O.D2Q9)
+    near = [True] * ny if masked_everywhere else _near_rows(mask)
+    tasks = _tasks_2d(ny, nx, yc, near, ym)
+    assert any(t[3] for t in tasks)
     stored, ref = _start(O.D2Q9, (1, ny, nx), 0.8, 3 / 16, solid=mask[None])
-    got = _two_step_2d(stored, e, opp, 0.8, 3 / 16, yc, solid=mask[None], near_only=near_only)
+    got = _two_step_2d(stored, e, opp, 0.8, 3 / 16, tasks, solid=mask[None])
     fluid = mask == 0
     assert not np.isnan(got[:, fluid]).any()
     assert np.abs(got[:, fluid] - ref[:, 0][:, fluid]).max() < 1e-14
