@@ -202,6 +202,18 @@ __device__ __forceinline__ void shifted_moments(const C (&h)[L::Q], C &drho, C &
     });
 }
 
+// The first pair whose first direction has a nonzero component on axis a
+// (0, 1, 2 = x, y, z), -1 if none.
+template <class L>
+__host__ __device__ constexpr int first_pair_on(int a)
+{
+    for (int p = 0; p < L::NP; ++p) {
+        const int i = L::pair_first(p);
+        if ((a == 0 ? L::ex(i) : (a == 1 ? L::ey(i) : L::ez(i))) != 0) return p;
+    }
+    return -1;
+}
+
 // In-place collision of one node.  Returns rho and u through the
 // references (used by the fused diagnostics).
 // GHOST = false gives standard TRT (Eq. collision_TRT: the ghost modes
@@ -217,24 +229,37 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
         sp[p] = h[i] + h[j];
         dp[p] = h[i] - h[j];
     });
+    // each momentum sum starts from its first term (not from 0 + term,
+    // which only differs in the sign of a zero sum; no result changes)
     C drho = h[0], jx = C(0), jy = C(0), jz = C(0);
     static_for<L::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         constexpr int i = L::pair_first(p);
         drho += sp[p];
-        if constexpr (L::ex(i) == 1) jx += dp[p];
-        if constexpr (L::ex(i) == -1) jx -= dp[p];
-        if constexpr (L::ey(i) == 1) jy += dp[p];
-        if constexpr (L::ey(i) == -1) jy -= dp[p];
-        if constexpr (L::ez(i) == 1) jz += dp[p];
-        if constexpr (L::ez(i) == -1) jz -= dp[p];
+        if constexpr (L::ex(i) != 0) {
+            if constexpr (first_pair_on<L>(0) == p) jx = L::ex(i) == 1 ? dp[p] : -dp[p];
+            else if constexpr (L::ex(i) == 1) jx += dp[p];
+            else jx -= dp[p];
+        }
+        if constexpr (L::ey(i) != 0) {
+            if constexpr (first_pair_on<L>(1) == p) jy = L::ey(i) == 1 ? dp[p] : -dp[p];
+            else if constexpr (L::ey(i) == 1) jy += dp[p];
+            else jy -= dp[p];
+        }
+        if constexpr (L::ez(i) != 0) {
+            if constexpr (first_pair_on<L>(2) == p) jz = L::ez(i) == 1 ? dp[p] : -dp[p];
+            else if constexpr (L::ez(i) == 1) jz += dp[p];
+            else jz -= dp[p];
+        }
     });
     const C rho = C(1) + drho;
     const C inv = C(1) / rho;
     const C ux = jx * inv + r.hgx;
     const C uy = jy * inv + r.hgy;
-    const C uz = jz * inv + r.hgz;
-    const C uu = ux * ux + uy * uy + uz * uz;
+    // 2D: u_z = 0 exactly (no z momentum, no z force)
+    const C uz = L::D == 3 ? jz * inv + r.hgz : C(0);
+    C uu = ux * ux + uy * uy;
+    if constexpr (L::D == 3) uu = uu + uz * uz;
     const C m15uu = C(-1.5) * uu;
 
     C pg0 = C(0), pg[L::NP];
