@@ -165,12 +165,12 @@ int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
 /* Steps per pass over the populations (1 or 2; default 2).  With 2, pairs
  * of steps run as one kernel that keeps the first step's results in LDS
  * (temporal blocking) where the configuration allows it and it measured
- * faster: periodic boundaries, PTRT_MODEL_PTRT and PTRT_FORCING_SCHEME2,
- * and either D3Q19 in FP32 or FP64 without solid nodes, nx a multiple of
- * 64 and ny >= 4, or D2Q9 in FP32 or FP64 (with solid nodes: from 2^20
- * nodes on, while at most 30 % of the rows lie in row chunks with a solid
- * within one row); every other case, and an odd last step, runs one step
- * per pass.  Results are bit-identical either way.
+ * faster: PTRT_MODEL_PTRT and PTRT_FORCING_SCHEME2, and either D3Q19 in
+ * FP32 or FP64 with periodic boundaries and without solid nodes, nx a
+ * multiple of 64 and ny >= 4, or D2Q9 in FP32 or FP64 (with solid nodes or
+ * open x: from 2^20 nodes on, while at most 30 % of the rows lie in row
+ * chunks with a solid within one row); every other case, and an odd last
+ * step, runs one step per pass.  Results are bit-identical either way.
  * Allowed at any time (waits for the handle's stream). */
 int ptrt_set_steps_per_pass(ptrt_ctx *ctx, int steps);
 

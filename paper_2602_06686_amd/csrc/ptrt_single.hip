@@ -38,8 +38,8 @@ struct ptrt_ctx {
     std::vector<uint8_t> h_mask, h_near;
     uint8_t *d_mask = nullptr, *d_near = nullptr;
     // D2Q9 with solids: two-step tasks without / with solids near their rows
-    int4 *d_tasks = nullptr; // plain tasks, then masked tasks
-    int n_plain = 0, n_masked = 0;
+    int4 *d_tasks = nullptr; // plain tasks, then special (masked / open) ones
+    int n_plain = 0, n_special = 0;
     long long masked_rows = 0;
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
@@ -137,51 +137,62 @@ int ensure_allocated(ptrt_ctx *c)
         c->h_near = near_solid_rows(c->h_mask.data(), c->nx, c->ny, c->nz);
         HIPCHK(c, hipMalloc(&c->d_near, c->h_near.size()));
         HIPCHK(c, hipMemcpy(c->d_near, c->h_near.data(), c->h_near.size(), hipMemcpyHostToDevice));
-        if (c->lattice == PTRT_D2Q9) {
-            // the two-step kernel's tasks {0, x0, ys, ye}: strips of BX
-            // columns times chunks of yc rows with no solid within one row
-            // of rows ys - 1 ... ye; the rows of the other chunks in chunks
-            // of ym rows, ym by the same rule over those rows alone with
-            // twice the task target (the masked code waits for the mask
-            // before its pulls; a few rows near solids give short masked
-            // tasks, whose time is latency).  Measured, GLUPS with the
-            // masked rows in chunks of ym = yc, then by this rule: FP32
-            // channel 1024^2 50.5 -> 89.2, 2048^2 84.7 -> 101.0; FP32
-            // obstacle 1024^2 49.2 -> 81.6, 2048^2 84.4 -> 96.2; FP64 channel
-            // 1024^2 43.1 -> 57.9 (target x1, x2, x4, x8: obstacle 2048^2
-            // FP32 85.6 / 96.2 / 94.9 / 91.5)
-            using SH = Step2Shape2D<float>;
-            const int strips = (c->nx + SH::BX - 1) / SH::BX;
-            const int yc = step2_2d_rows(c->storage, c->nx, c->ny);
-            std::vector<int4> plain, masked;
-            std::vector<int2> near_chunks;
-            long long masked_rows = 0;
-            for (int ys = 0; ys < c->ny; ys += yc) {
-                const int ye = std::min(ys + yc, c->ny);
-                bool near = false;
+    }
+    if (c->lattice == PTRT_D2Q9 && (c->has_mask || c->open)) {
+        // the two-step kernel's tasks {0, x0, ys, ye}: strips of BX columns
+        // times chunks of yc rows with no solid within one row of rows
+        // ys - 1 ... ye (plain); the rows of the other chunks, and with open
+        // x every row of the first and last strip, in chunks of ym rows
+        // (special: the masked / open kernel), ym by the same rule over
+        // those rows alone with twice the task target (the masked code
+        // waits for the mask before its pulls; a few rows near solids give
+        // short special tasks, whose time is latency).  Measured, GLUPS
+        // with the masked rows in chunks of ym = yc, then by this rule:
+        // FP32 channel 1024^2 50.5 -> 89.2, 2048^2 84.7 -> 101.0; FP32
+        // obstacle 1024^2 49.2 -> 81.6, 2048^2 84.4 -> 96.2; FP64 channel
+        // 1024^2 43.1 -> 57.9 (target x1, x2, x4, x8: obstacle 2048^2
+        // FP32 85.6 / 96.2 / 94.9 / 91.5)
+        using SH = Step2Shape2D<float>;
+        const int strips = (c->nx + SH::BX - 1) / SH::BX;
+        const int yc = step2_2d_rows(c->storage, c->nx, c->ny);
+        std::vector<int4> plain, special;
+        struct Chunk {
+            int ys, ye;
+            std::vector<int> bxs; // strips whose tasks are special
+        };
+        std::vector<Chunk> spec;
+        long long masked_rows = 0, spec_strip_rows = 0;
+        for (int ys = 0; ys < c->ny; ys += yc) {
+            const int ye = std::min(ys + yc, c->ny);
+            bool near = false;
+            if (c->has_mask)
                 for (int y = ys - 1; y <= ye && !near; ++y)
                     near = c->h_near[(size_t)(((y % c->ny) + c->ny) % c->ny)] != 0;
-                if (near) {
-                    near_chunks.push_back(make_int2(ys, ye));
-                    masked_rows += ye - ys;
-                } else {
-                    for (int bx = 0; bx < strips; ++bx) plain.push_back(make_int4(0, bx * SH::BX, ys, ye));
-                }
+            if (near) masked_rows += ye - ys;
+            Chunk ch{ys, ye, {}};
+            for (int bx = 0; bx < strips; ++bx) {
+                const bool edge = c->open && (bx == 0 || bx == strips - 1);
+                if (near || edge)
+                    ch.bxs.push_back(bx);
+                else
+                    plain.push_back(make_int4(0, bx * SH::BX, ys, ye));
             }
-            const int ym = step2_2d_rows_for(c->storage, strips * masked_rows,
-                                             (long long)c->nx * masked_rows, 2);
-            for (const int2 &ch : near_chunks)
-                for (int ys = ch.x; ys < ch.y; ys += ym)
-                    for (int bx = 0; bx < strips; ++bx)
-                        masked.push_back(make_int4(0, bx * SH::BX, ys, std::min(ys + ym, ch.y)));
-            c->n_plain = (int)plain.size();
-            c->n_masked = (int)masked.size();
-            c->masked_rows = masked_rows;
-            plain.insert(plain.end(), masked.begin(), masked.end());
-            HIPCHK(c, hipMalloc(&c->d_tasks, sizeof(int4) * plain.size()));
-            HIPCHK(c, hipMemcpy(c->d_tasks, plain.data(), sizeof(int4) * plain.size(),
-                                hipMemcpyHostToDevice));
+            if (!ch.bxs.empty()) {
+                spec_strip_rows += (long long)ch.bxs.size() * (ye - ys);
+                spec.push_back(std::move(ch));
+            }
         }
+        const int ym = step2_2d_rows_for(c->storage, spec_strip_rows, (long long)SH::BX * spec_strip_rows, 2);
+        for (const Chunk &ch : spec)
+            for (int ys = ch.ys; ys < ch.ye; ys += ym)
+                for (int bx : ch.bxs)
+                    special.push_back(make_int4(0, bx * SH::BX, ys, std::min(ys + ym, ch.ye)));
+        c->n_plain = (int)plain.size();
+        c->n_special = (int)special.size();
+        c->masked_rows = masked_rows;
+        plain.insert(plain.end(), special.begin(), special.end());
+        HIPCHK(c, hipMalloc(&c->d_tasks, sizeof(int4) * plain.size()));
+        HIPCHK(c, hipMemcpy(c->d_tasks, plain.data(), sizeof(int4) * plain.size(), hipMemcpyHostToDevice));
     }
     const dim3 gg = gather_grid(c, c->nz);
     c->nparts = gg.x * gg.y * gg.z;
@@ -357,9 +368,9 @@ StepLaunch step_args(const ptrt_ctx *c, hipStream_t s)
     a.near = c->d_near;
     if (c->d_tasks) {
         a.tasks_plain = c->d_tasks;
-        a.tasks_masked = c->d_tasks + c->n_plain;
+        a.tasks_special = c->d_tasks + c->n_plain;
         a.n_plain = c->n_plain;
-        a.n_masked = c->n_masked;
+        a.n_special = c->n_special;
         a.masked_rows = c->masked_rows;
     }
     a.g = geom(c);

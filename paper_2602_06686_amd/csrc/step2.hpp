@@ -318,8 +318,14 @@ __device__ __forceinline__ void wave_lds_sync()
 // MASK = false): the first step pulls the node's own opposite population
 // where the source is solid, the second step likewise from the first
 // step's values of its own node, and solid second-step nodes are not
-// stored (as in the one-step kernel).
-template <class S, bool NT, bool MASK>
+// stored (as in the one-step kernel).  OPEN: x is not periodic (velocity
+// inlet at x = 0, Zou-He outlet at x = nx - 1, as pull<..., OPEN>): in
+// both steps the populations entering the inlet node are its own outgoing
+// ones plus 6 w_i u_in (the second step reads them from its own node's
+// first-step values, like bounce-back), and the outlet node's entering
+// ones come from zou_he_east; the first-step values across the x seam are
+// then never read.
+template <class S, bool NT, bool MASK, bool OPEN = false>
 __device__ __forceinline__ void
 step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
               const Geom &g, const Coef<D2Q9, typename Codec<S>::compute> &r, S *lds, int x0,
@@ -327,7 +333,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
 {
     using L = D2Q9;
     using C = typename Codec<S>::compute;
-    using SH = Step2Shape2D<S, MASK>;
+    using SH = Step2Shape2D<S, MASK || OPEN>;
     using K = typename SH::K;
     constexpr int W = SH::W, BX = SH::BX;
     const int lane = (int)(threadIdx.x & 63);
@@ -389,8 +395,22 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
                 if (solid(js, -L::ex(i)))
                     p = sb + o[J] + (size_t)L::opp(i) * dir_bytes + xo_0;
             }
+            if constexpr (OPEN && L::ex(i) == 1) {
+                if (ax == 0) p = sb + o[J] + (size_t)L::opp(i) * dir_bytes + xo_0;
+            }
             raw[i] = *reinterpret_cast<const S *>(p);
         });
+    };
+    // open x: the inlet term on the populations entering node x = 0 (their
+    // values are already the node's own outgoing ones), Zou-He at nx - 1
+    auto open_fix = [&](C(&h)[L::Q], int x) {
+        if (x == 0) {
+            static_for<L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (L::ex(i) == 1) h[i] = h[i] + C(6.0 * L::w(i)) * C(g.uin);
+            });
+        }
+        if (x == g.nx - 1) zou_he_east(h, C(g.drhoout));
     };
     auto finish_a = [&](int it, const S (&raw)[L::Q]) {
         C h[L::Q];
@@ -398,6 +418,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
             constexpr int i = decltype(ic)::value;
             h[i] = Codec<S>::load(&raw[i]);
         });
+        if constexpr (OPEN) open_fix(h, ax);
         C rho, ux, uy, uz;
         collide<L, C, true>(h, r, rho, ux, uy, uz);
         static_for<L::Q>([&](auto ic) {
@@ -436,8 +457,13 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
                     if (solid(1 - L::ey(i), -L::ex(i)))
                         at_i = lds_at(co, K::index(io), (it - 1) % K::slots(co), lane);
                 }
+                if constexpr (OPEN && L::ex(i) == 1) {
+                    constexpr int io = L::opp(i), co = K::cls(io);
+                    if (bxg == 0) at_i = lds_at(co, K::index(io), (it - 1) % K::slots(co), lane);
+                }
                 h[i] = Codec<S>::load(&lds[at_i]);
             });
+            if constexpr (OPEN) open_fix(h, bxg);
             C rho, ux, uy, uz;
             collide<L, C, true>(h, r, rho, ux, uy, uz);
             char *db = reinterpret_cast<char *>(dst) + o[1];
@@ -481,14 +507,14 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
 // the last partial.  The NW waves of a workgroup run independent tasks
 // (neighbouring strips of one chunk).  Eight waves per SIMD: FP32 fits in
 // 64 VGPRs (measured +1.5 % at 4096^2).
-template <class S, bool NT, int NW, bool MASK>
+template <class S, bool NT, int NW, bool MASK, bool OPEN>
 __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
            const int4 *__restrict__ task_list, Geom g, Coef<D2Q9, typename Codec<S>::compute> r,
            int yc, int strips, int tasks)
 {
-    using SH = Step2Shape2D<S, MASK>;
+    using SH = Step2Shape2D<S, MASK || OPEN>;
     __shared__ S lds_all[NW * SH::K::planes * SH::W];
     int wg, unused_y, unused_z;
     xcd_block(wg, unused_y, unused_z);
@@ -507,8 +533,8 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__rest
         ys = by * yc;
         ye = min(ys + yc, g.ny);
     }
-    step2_2d_task<S, NT, MASK>(src, dst, mask, g, r, lds_all + w * (SH::K::planes * SH::W), x0,
-                               ys, ye);
+    step2_2d_task<S, NT, MASK, OPEN>(src, dst, mask, g, r, lds_all + w * (SH::K::planes * SH::W),
+                                     x0, ys, ye);
 }
 
 } // namespace ptrt

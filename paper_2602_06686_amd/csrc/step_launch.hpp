@@ -26,11 +26,12 @@ struct StepLaunch {
     void *phi = nullptr; // Phi field in the compute type (FORCE_II_G)
     bool open = false;   // D2Q9 inlet / outlet in x (values in g)
     hipStream_t stream = nullptr;
-    // D2Q9 with solids, two steps per pass: the tasks {unused, x0, ys, ye}
-    // without and with a solid within one row of their rows, and the rows
-    // the latter cover
-    const int4 *tasks_plain = nullptr, *tasks_masked = nullptr;
-    int n_plain = 0, n_masked = 0;
+    // D2Q9 with solids or open x, two steps per pass: the tasks {unused,
+    // x0, ys, ye} for the mask-free periodic kernel and the special ones
+    // (a solid within one row of their rows, or a strip at an open x
+    // boundary), and the rows of the chunks near solids
+    const int4 *tasks_plain = nullptr, *tasks_special = nullptr;
+    int n_plain = 0, n_special = 0;
     long long masked_rows = 0;
 };
 
@@ -74,7 +75,8 @@ inline int step2_2d_rows(int storage, int nx, int ny)
 template <class L>
 bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
 {
-    if (a.open || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II) return false;
+    if ((a.open && L::D != 2) || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II)
+        return false;
     if constexpr (L::D == 2) {
         // measured against one step per pass: a gain at every size in FP32
         // and FP64 (64^2 ... 4096^2, 8 - 30 %); none in FP16 / BF16, whose
@@ -87,9 +89,11 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
         // 75.4 -> 89.0, 2048^2 81.8 -> 100.7, 4096^2 86.1 -> 102.2, an
         // obstacle over 1/8 of the rows 4096^2 85.8 -> 101.1; FP64 channel
         // 1024^2 41.8 -> 58.3, 4096^2 42.2 -> 64.0; at 512^2 both lost 10 %)
-        if (a.has_mask) {
+        // with open x (inlet / outlet strips in the special launch), the
+        // same floor (measured on the 1050^2 square cylinder, below)
+        if (a.has_mask || a.open) {
             if ((long long)a.g.nx * a.g.ny < (1LL << 20)) return false;
-            if (!a.tasks_plain || !a.tasks_masked || a.n_plain + a.n_masked == 0) return false;
+            if (!a.tasks_plain || !a.tasks_special || a.n_plain + a.n_special == 0) return false;
             if (a.masked_rows > 0.3 * a.g.ny) return false;
         }
         dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
@@ -109,24 +113,31 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                     *pass_bytes = (2.0 * L::Q * sizeof(S) + (a.has_mask ? 1.0 : 0.0)) *
                                   a.g.nx * a.g.ny;
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
-                auto go = [&](auto mc, const int4 *list, int n) {
-                    constexpr bool M = decltype(mc)::value;
+                auto go = [&](auto mc, auto oc, const int4 *list, int n) {
+                    constexpr bool M = decltype(mc)::value, O = decltype(oc)::value;
                     if (n == 0) return;
                     const dim3 grid((n + NW - 1) / NW, 1, 1);
                     if (a.nt)
-                        hipLaunchKernelGGL((k_step2_2d<S, true, NW, M>), grid, dim3(SH::W * NW), 0,
-                                           a.stream, (const S *)a.src, (S *)a.dst, a.mask, list,
-                                           a.g, r, yc, strips, n);
+                        hipLaunchKernelGGL((k_step2_2d<S, true, NW, M, O>), grid, dim3(SH::W * NW),
+                                           0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
+                                           list, a.g, r, yc, strips, n);
                     else
-                        hipLaunchKernelGGL((k_step2_2d<S, false, NW, M>), grid, dim3(SH::W * NW),
+                        hipLaunchKernelGGL((k_step2_2d<S, false, NW, M, O>), grid, dim3(SH::W * NW),
                                            0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
                                            list, a.g, r, yc, strips, n);
                 };
-                if (a.has_mask) {
-                    go(std::false_type{}, a.tasks_plain, a.n_plain);
-                    go(std::true_type{}, a.tasks_masked, a.n_masked);
+                using F = std::false_type;
+                using T = std::true_type;
+                if (a.has_mask || a.open) {
+                    go(F{}, F{}, a.tasks_plain, a.n_plain);
+                    if (a.has_mask && a.open)
+                        go(T{}, T{}, a.tasks_special, a.n_special);
+                    else if (a.has_mask)
+                        go(T{}, F{}, a.tasks_special, a.n_special);
+                    else
+                        go(F{}, T{}, a.tasks_special, a.n_special);
                 } else {
-                    go(std::false_type{}, nullptr, tasks);
+                    go(F{}, F{}, nullptr, tasks);
                 }
             }
             return PTRT_OK;

@@ -237,3 +237,55 @@ def test_two_steps_per_pass_matches_oracle():
     err = A.rel_l2(ug, uo)
     print(f"two steps per pass, 100 steps, velocity rel L2 {err:.3e}", flush=True)
     assert err < 1e-5
+
+
+def _run_open(shape, storage, steps, spp, mask=None, seed=8):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    rho, u = I.random_fields(rng, shape, umax=0.02)
+    u[0] += 0.03
+    with P.Lattice(0, nx, ny, nz, 0.7, 3 / 16, storage=storage, solid_mask=mask,
+                   open_x=(0.03, 1.0), steps_per_pass=spp) as G:
+        G.init_equilibrium(rho, u[:2])
+        G.step(steps)
+        return G.populations(), G.last_pass()[0]
+
+
+def _open_masks():
+    """Open-x layouts of at least 2^20 nodes: no solids (last strip partial),
+    a square cylinder (the benchmark's shape), channel walls at y = 0 and
+    ny - 1, and a width that is a multiple of 62 (the last strip's halo
+    column wraps onto the inlet)."""
+    out = [((1, 1030, 1040), None)]
+    n = 1050
+    m = np.zeros((1, n, n), dtype=np.uint8)
+    c0 = n // 2 - 10
+    m[0, c0:c0 + 21, c0:c0 + 21] = 1
+    out.append(((1, n, n), m))
+    m = np.zeros((1, 1030, 1040), dtype=np.uint8)
+    m[0, 0, :] = m[0, -1, :] = 1
+    out.append(((1, 1030, 1040), m))
+    out.append(((1, 1000, 1054), None))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("steps", [2, 7, 40])
+def test_two_steps_per_pass_d2q9_open_bitwise(storage, case, steps):
+    """Open x (velocity inlet, Zou-He outlet): the boundary strips run the
+    open kernel in the special launch; bit for bit against one step per
+    pass on every fluid node."""
+    shape, mask = _open_masks()[case]
+    print_case("D2Q9 open x, steps per pass 2 vs 1", storage, shape, steps)
+    a, pa = _run_open(shape, storage, steps, 1, mask)
+    b, pb = _run_open(shape, storage, steps, 2, mask)
+    assert pa == 1 and pb == (2 if steps % 2 == 0 else 1)
+    fluid = np.broadcast_to(True if mask is None else mask == 0, a.shape)
+    assert np.array_equal(a[fluid], b[fluid])
+
+
+def test_two_steps_per_pass_d2q9_open_floor():
+    print_case("D2Q9 open x below 2^20 nodes: one step per pass")
+    _, p = _run_open((1, 1000, 1000), "f64", 4, 2)
+    assert p == 1
