@@ -47,7 +47,7 @@ def test_precision_form_64cube(setting):
     _, uo = ora.moments()
     wo = _vorticity(uo)
     errs = {}
-    # At 1/tau- = 1.6 the FP16 bar is the benchmark spec's 1e-3.  At Lambda = 1/4
+    # At 1/tau- = 1.6 the FP16 bar is the 1e-3 accuracy target.  At Lambda = 1/4
     # (tau- = 262 here) the third-order modes are almost undamped and the
     # FP64 run itself blows up after ~1000 steps, so low-precision rounding
     # noise is hardly damped: those errors are reported, with loose bounds.

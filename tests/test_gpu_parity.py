@@ -1,7 +1,7 @@
 """GPU parity of the HIP path (called through the C interface) against the
 FP64 oracle, on the same seeded inputs.
 
-Tolerances (spec bars; the arithmetic behind them is in the design doc):
+Tolerances:
 * FP64 storage/arithmetic: 1e-12 relative (max-norm of populations over the
   max population, and relative L2 of the velocity);
 * FP32: 1e-5 relative L2 of the velocity after 1000 steps of the 64^2
