@@ -166,8 +166,9 @@ int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
  * of steps run as one kernel that keeps the first step's results in LDS
  * (temporal blocking) where the configuration allows it and it measured
  * faster: PTRT_MODEL_PTRT and PTRT_FORCING_SCHEME2, and either D3Q19 in
- * FP32 or FP64 with periodic boundaries and without solid nodes, nx a
- * multiple of 64 and ny >= 4, or D2Q9 in FP32 or FP64 (with solid nodes or
+ * FP32 or FP64 with nx a multiple of 64 and ny >= 4 (with solid nodes:
+ * from 2^24 nodes on, while at most 5 % of the kernel's column chunks have
+ * a solid within one row), or D2Q9 in FP32 or FP64 (with solid nodes or
  * open x: from 2^20 nodes on, while at most 30 % of the rows lie in row
  * chunks with a solid within one row); every other case, and an odd last
  * step, runs one step per pass.  Results are bit-identical either way.

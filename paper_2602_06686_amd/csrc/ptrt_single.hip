@@ -138,6 +138,23 @@ int ensure_allocated(ptrt_ctx *c)
         HIPCHK(c, hipMalloc(&c->d_near, c->h_near.size()));
         HIPCHK(c, hipMemcpy(c->d_near, c->h_near.data(), c->h_near.size(), hipMemcpyHostToDevice));
     }
+    if (c->lattice == PTRT_D3Q19 && c->has_mask) {
+        // the 3D two-step pass with solids: mask-free and masked column
+        // chunks (none when the pass does not apply)
+        std::vector<int4> plain, special;
+        bool ok = false;
+        if (c->storage == PTRT_F32)
+            ok = step2_3d_task_lists<D3Q19, float>(c->geo, c->h_near.data(), plain, special);
+        else if (c->storage == PTRT_F64)
+            ok = step2_3d_task_lists<D3Q19, double>(c->geo, c->h_near.data(), plain, special);
+        if (ok && (!plain.empty() || !special.empty())) {
+            c->n_plain = (int)plain.size();
+            c->n_special = (int)special.size();
+            plain.insert(plain.end(), special.begin(), special.end());
+            HIPCHK(c, hipMalloc(&c->d_tasks, sizeof(int4) * plain.size()));
+            HIPCHK(c, hipMemcpy(c->d_tasks, plain.data(), sizeof(int4) * plain.size(), hipMemcpyHostToDevice));
+        }
+    }
     if (c->lattice == PTRT_D2Q9 && (c->has_mask || c->open)) {
         // the two-step kernel's tasks {0, x0, ys, ye}: strips of BX columns
         // times chunks of yc rows with no solid within one row of rows

@@ -1,5 +1,6 @@
-// Two fused steps per pass over the populations (temporal blocking) for 3D
-// lattices without solids, P-TRT with the default forcing.
+// Two fused steps per pass over the populations (temporal blocking), P-TRT
+// with the default forcing: 3D (k_step2 over a grid, k_step2_list over
+// task lists with solids) and 2D (k_step2_2d, below).
 //
 // A workgroup owns a column of BX = 64 by BY nodes in (x, y) and a chunk of
 // ZC planes in z, and marches upwards through its planes.  For each plane k
@@ -64,7 +65,7 @@ struct Step2Classes {
 };
 
 // Workgroup rows for the storage type.
-template <class L, class S>
+template <class L, class S, bool MASK = false>
 struct Step2Shape {
     static constexpr int BX = 64;
     // measured: a gain for D3Q19 in FP32 and FP64 (one workgroup per CU,
@@ -76,7 +77,9 @@ struct Step2Shape {
     // one wave per interior row; the AY + 1 first-step tasks (AY rows and
     // the halo columns) are shared out over them, at most two per wave
     static constexpr int WAVES = BY;
-    using K = Step2Classes<L>;
+    // MASK: the e_z = -1 class keeps the plane below too (bounce-back reads
+    // the node's own first-step values of the previous plane)
+    using K = Step2Classes<L, L::D - 1, MASK>;
     static constexpr size_t lds_bytes = (size_t)K::planes * AP * sizeof(S);
     static constexpr bool available =
         BY >= 3 && lds_bytes <= 163840 && AY + 1 <= 2 * WAVES;
@@ -103,22 +106,22 @@ __device__ __forceinline__ void collide_ptrt(C (&h)[L::Q], const Coef<L, C> &r, 
         collide<L, C, true>(h, r, rho, ux, uy, uz);
 }
 
-template <class L, class S, bool NT>
-__global__ void __launch_bounds__((64 * Step2Shape<L, S>::WAVES))
-k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
-        Coef<L, typename Codec<S>::compute> r, int zc)
+// One column chunk of the pass, run by the workgroup: second steps for
+// planes zs ... ze - 1 (ze > zs) of the column x0 ... x0 + BX - 1, y0 ...
+// y0 + BY - 1, first steps in lds.  MASK: halfway bounce-back in both
+// steps (the first step pulls through pull<L, S, true>; the second takes
+// the node's own first-step value of the opposite direction where the
+// source node is solid, and solid nodes are not stored).
+template <class L, class S, bool NT, bool MASK>
+__device__ __forceinline__ void
+step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+              const Geom &g, const Coef<L, typename Codec<S>::compute> &r, S *lds, int x0, int y0,
+              int zs, int ze)
 {
     using C = typename Codec<S>::compute;
-    using SH = Step2Shape<L, S>;
+    using SH = Step2Shape<L, S, MASK>;
     using K = typename SH::K;
-    constexpr int BX = SH::BX, BY = SH::BY, AX = SH::AX, AY = SH::AY, AP = SH::AP;
-    __shared__ S lds[K::planes * AP];
-
-    int bx, by, bz;
-    xcd_block(bx, by, bz);
-    const int x0 = bx * BX, y0 = by * BY;
-    const int zs = bz * zc;
-    const int ze = min(zs + zc, g.nz);
+    constexpr int BY = SH::BY, AX = SH::AX, AY = SH::AY, AP = SH::AP;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
     auto wrapc = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
@@ -150,7 +153,7 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         const int gx = wrapc(x0 - 1 + ax, g.nx);
         const int gy = wrapc(y0 - 1 + ay, g.ny);
         const int gz = wrapc(k, g.nz);
-        pull<L, S, false>(src, nullptr, g, gx, gy, gz, raw, [](const S *p) { return *p; });
+        pull<L, S, MASK>(src, mask, g, gx, gy, gz, raw, [](const S *p) { return *p; });
     };
     // the same for a row task (ay < AY): the nine source rows are uniform
     // across the wave (scalar offsets, each computed once), the lane's three
@@ -215,7 +218,7 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     // row tasks in FP64 take load_row (measured at 256^3: FP64 +5.6 %;
     // FP32 +1 % at 256^3 and -1.7 % at 512^3, so FP32 keeps load_a)
     auto load_both = [&](int k) {
-        if constexpr (sizeof(S) == 8) {
+        if constexpr (sizeof(S) == 8 && !MASK) {
             if (has1) {
                 if (t1 < AY)
                     load_row(t1, k, raw1);
@@ -251,32 +254,89 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         {
             // B: second step at interior node (x0 + lane, y0 + w, k - 1)
             const int ax = lane + 1, ay = w + 1;
-            C h[L::Q];
-            static_for<L::Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int c = K::cls(i);
-                // plane of the source: k (c = 0), k - 1 (c = 1), k - 2 (c = 2)
-                const int slot = (it - c) % K::slots(c);
-                const int a = (ay - L::ey(i)) * AX + (ax - L::ex(i));
-                h[i] = Codec<S>::load(&lds[lds_at(c, K::index(i), slot, a)]);
-            });
-            C rho, ux, uy, uz;
-            collide_ptrt<L, C>(h, r, rho, ux, uy, uz);
             // past ny (the last workgroup row when BY does not divide ny)
             // the wrapped row is computed again: the same values as its
             // own workgroup writes
             const int gz = wrapc(k - 1, g.nz);
-            const unsigned row = (unsigned)gz * (unsigned)g.ny + (unsigned)wrapc(y0 + w, g.ny);
-            static_for<L::Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                Codec<S>::template store<NT>(at(dst, g, i, row, x0 + lane), h[i]);
-            });
+            const int gy = wrapc(y0 + w, g.ny);
+            const unsigned row = (unsigned)gz * (unsigned)g.ny + (unsigned)gy;
+            bool store = true;
+            if constexpr (MASK) store = !mask[row * (unsigned)g.nx + (unsigned)(x0 + lane)];
+            C h[L::Q];
+            if constexpr (MASK) {
+                const Nbr n(g, x0 + lane, gy, gz);
+                static_for<L::Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    constexpr int c = K::cls(i);
+                    const int slot = (it - c) % K::slots(c);
+                    int at_i = lds_at(c, K::index(i), slot, (ay - L::ey(i)) * AX + (ax - L::ex(i)));
+                    if constexpr (i != 0) {
+                        // solid source: the node's own first-step value of
+                        // the opposite direction, plane k - 1 (iteration it - 1)
+                        int sx;
+                        unsigned srow;
+                        source_of<L, i>(g, n, x0 + lane, gy, gz, sx, srow);
+                        constexpr int io = L::opp(i), co = K::cls(io);
+                        if (mask[srow * (unsigned)g.nx + (unsigned)sx])
+                            at_i = lds_at(co, K::index(io), (it - 1) % K::slots(co), ay * AX + ax);
+                    }
+                    h[i] = Codec<S>::load(&lds[at_i]);
+                });
+            } else {
+                static_for<L::Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    constexpr int c = K::cls(i);
+                    // plane of the source: k (c = 0), k - 1 (c = 1), k - 2 (c = 2)
+                    const int slot = (it - c) % K::slots(c);
+                    const int a = (ay - L::ey(i)) * AX + (ax - L::ex(i));
+                    h[i] = Codec<S>::load(&lds[lds_at(c, K::index(i), slot, a)]);
+                });
+            }
+            C rho, ux, uy, uz;
+            collide_ptrt<L, C>(h, r, rho, ux, uy, uz);
+            if (store) {
+                static_for<L::Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    Codec<S>::template store<NT>(at(dst, g, i, row, x0 + lane), h[i]);
+                });
+            }
         }
         lds_barrier();
         if (k == ze) break;
         finish_both(it + 1);
         load_both(min(k + 2, ze));
     }
+}
+
+// Grid (x blocks, y blocks, z chunks of zc planes), without solids.
+template <class L, class S, bool NT>
+__global__ void __launch_bounds__((64 * Step2Shape<L, S>::WAVES))
+k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
+        Coef<L, typename Codec<S>::compute> r, int zc)
+{
+    using SH = Step2Shape<L, S>;
+    __shared__ S lds[SH::K::planes * SH::AP];
+    int bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int zs = bz * zc;
+    step2_3d_task<L, S, NT, false>(src, dst, nullptr, g, r, lds, bx * SH::BX, by * SH::BY, zs,
+                                   min(zs + zc, g.nz));
+}
+
+// Task list (with solids): workgroup t runs tasks[t] = {x0, y0, zs, ze}.
+template <class L, class S, bool NT, bool MASK>
+__global__ void __launch_bounds__((64 * Step2Shape<L, S, MASK>::WAVES))
+k_step2_list(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
+             Geom g, Coef<L, typename Codec<S>::compute> r, const int4 *__restrict__ tasks,
+             int ntasks)
+{
+    using SH = Step2Shape<L, S, MASK>;
+    __shared__ S lds[SH::K::planes * SH::AP];
+    int t, unused_y, unused_z;
+    xcd_block(t, unused_y, unused_z);
+    if (t >= ntasks) return;
+    const int4 tk = tasks[t];
+    step2_3d_task<L, S, NT, MASK>(src, dst, mask, g, r, lds, tk.x, tk.y, tk.z, tk.w);
 }
 
 // Two fused steps per pass for D2Q9 without solids (the 2D counterpart of

@@ -5,6 +5,7 @@
 #pragma once
 
 #include <algorithm>
+#include <vector>
 
 #include "host_common.hpp"
 #include "step2.hpp"
@@ -70,6 +71,104 @@ inline int step2_2d_rows(int storage, int nx, int ny)
 {
     const long long strips = (nx + Step2Shape2D<float>::BX - 1) / Step2Shape2D<float>::BX;
     return step2_2d_rows_for(storage, strips * ny, (long long)nx * ny);
+}
+
+// Planes per z chunk of the 3D two-step pass (grid or task list).
+template <class L, class S>
+int step2_3d_zc(const Geom &g)
+{
+    using SH = Step2Shape<L, S>;
+    // z chunks: the workgroups run in rounds of R = (workgroups
+    // resident per CU) x CUs, and a workgroup's time grows with
+    // its zc + 2 first-step planes, so zc minimises
+    // ceil(cols * ceil(nz / zc) / R) * (zc + 2) (measured at
+    // 384^3: 576 workgroups of the whole depth, 1.1 rounds,
+    // 34.9 GLUPS)
+    const int rows = (g.ny + SH::BY - 1) / SH::BY;
+    const long long cols = (long long)(g.nx / SH::BX) * rows;
+    static int resident = 0; // per process: one device type
+    if (resident == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(&k_step2<L, S, true>),
+                64 * SH::WAVES, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            per_cu <= 0 || cus <= 0)
+            resident = 512;
+        else
+            resident = per_cu * cus;
+    }
+    // candidates: zc = ceil(nz / c) for c = 1, 2, ... chunks, down
+    // to 8 planes or until the last round is under 1/16 of the
+    // work (more chunks then only add halo planes)
+    int zc = g.nz;
+    double best = -1.0;
+    for (int c = 1;; ++c) {
+        const int z = (g.nz + c - 1) / c;
+        const long long wgs = cols * ((g.nz + z - 1) / z);
+        const double cost = (double)((wgs + resident - 1) / resident) * (z + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            zc = z;
+        }
+        if (z <= 8 || wgs >= 16LL * resident) break;
+    }
+    return zc;
+}
+
+// Task lists of the 3D two-step pass with solids: the column chunks {x0,
+// y0, zs, ze} of the grid launch (zc planes) none of whose first-step rows
+// y0 - 1 ... y0 + BY, zs - 1 ... ze has a solid within one row (near, per
+// row z ny + y) go to the mask-free list; the others, split into chunks of
+// ZM planes, to the masked list (short chunks: the masked code is slower,
+// and with few such columns their time is latency).  false when the pass
+// does not apply, below 2^24 nodes or with more than 5 % of the chunks
+// masked (measured, one step -> two, GLUPS FP32 / FP64: channel 256^3,
+// 3 % masked, 40.0 -> 45.2 / 19.5 -> 22.6; a cube over 1/8 of each axis
+// at 256^3, 16 % masked, 39.7 -> 36.4 / 19.6 -> 17.7; channel 128^3, 6 %
+// masked, 36.2 -> 25.4 / 19.1 -> 15.0).
+template <class L, class S>
+bool step2_3d_task_lists(const Geom &g, const uint8_t *near, std::vector<int4> &plain,
+                         std::vector<int4> &special)
+{
+    using SH = Step2Shape<L, S>;
+    constexpr int ZM = 8;
+    if constexpr (!SH::available) {
+        return false;
+    } else {
+        if (g.nx % SH::BX != 0 || g.ny < SH::BY) return false;
+        if ((long long)g.nx * g.ny * g.nz < (1LL << 24)) return false;
+        const int zc = step2_3d_zc<L, S>(g);
+        const int rows = (g.ny + SH::BY - 1) / SH::BY, xb = g.nx / SH::BX;
+        auto wrap = [](int v, int n) { return ((v % n) + n) % n; };
+        long long chunks = 0, masked = 0;
+        std::vector<int4> spec;
+        for (int zs = 0; zs < g.nz; zs += zc) {
+            const int ze = std::min(zs + zc, g.nz);
+            for (int by = 0; by < rows; ++by) {
+                const int y0 = by * SH::BY;
+                bool nr = false;
+                for (int z = zs - 1; z <= ze && !nr; ++z)
+                    for (int y = y0 - 1; y <= y0 + SH::BY && !nr; ++y)
+                        nr = near[(size_t)wrap(z, g.nz) * g.ny + wrap(y, g.ny)] != 0;
+                ++chunks;
+                masked += nr;
+                for (int bx = 0; bx < xb; ++bx) {
+                    if (!nr) {
+                        plain.push_back(make_int4(bx * SH::BX, y0, zs, ze));
+                    } else {
+                        for (int z = zs; z < ze; z += ZM)
+                            spec.push_back(make_int4(bx * SH::BX, y0, z, std::min(z + ZM, ze)));
+                    }
+                }
+            }
+        }
+        if (masked * 20 > chunks) return false;
+        special = spec;
+        return true;
+    }
 }
 
 template <class L>
@@ -144,7 +243,7 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
         });
         return true;
     } else {
-        if (a.has_mask) return false;
+        if (a.has_mask && (!a.tasks_plain || !a.tasks_special)) return false;
         bool launched = false;
         dispatch_storage(a.storage, false, [&](auto st, auto) -> int {
             using S = typename decltype(st)::type;
@@ -152,43 +251,8 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
             using SH = Step2Shape<L, S>;
             if constexpr (SH::available) {
                 if (a.g.nx % SH::BX != 0 || a.g.ny < SH::BY) return PTRT_OK;
-                // z chunks: the workgroups run in rounds of R = (workgroups
-                // resident per CU) x CUs, and a workgroup's time grows with
-                // its zc + 2 first-step planes, so zc minimises
-                // ceil(cols * ceil(nz / zc) / R) * (zc + 2) (measured at
-                // 384^3: 576 workgroups of the whole depth, 1.1 rounds,
-                // 34.9 GLUPS)
                 const int rows = (a.g.ny + SH::BY - 1) / SH::BY;
-                const long long cols = (long long)(a.g.nx / SH::BX) * rows;
-                static int resident = 0; // per process: one device type
-                if (resident == 0) {
-                    int per_cu = 0, dev = 0, cus = 0;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &per_cu, reinterpret_cast<const void *>(&k_step2<L, S, true>),
-                            64 * SH::WAVES, 0) != hipSuccess ||
-                        hipGetDevice(&dev) != hipSuccess ||
-                        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                            hipSuccess ||
-                        per_cu <= 0 || cus <= 0)
-                        resident = 512;
-                    else
-                        resident = per_cu * cus;
-                }
-                // candidates: zc = ceil(nz / c) for c = 1, 2, ... chunks, down
-                // to 8 planes or until the last round is under 1/16 of the
-                // work (more chunks then only add halo planes)
-                int zc = a.g.nz;
-                double best = -1.0;
-                for (int c = 1;; ++c) {
-                    const int z = (a.g.nz + c - 1) / c;
-                    const long long wgs = cols * ((a.g.nz + z - 1) / z);
-                    const double cost = (double)((wgs + resident - 1) / resident) * (z + 2);
-                    if (best < 0 || cost < best) {
-                        best = cost;
-                        zc = z;
-                    }
-                    if (z <= 8 || wgs >= 16LL * resident) break;
-                }
+                const int zc = step2_3d_zc<L, S>(a.g);
                 const dim3 grid(a.g.nx / SH::BX, rows, (a.g.nz + zc - 1) / zc);
                 const dim3 block(64 * SH::WAVES, 1, 1);
                 // the state read once and written once: the first step's
@@ -196,12 +260,31 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                 // on one XCD (measured: HBM reads 1.03x the state)
                 if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * a.g.nz * L::Q * sizeof(S);
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
-                if (a.nt)
+                if (a.has_mask) {
+                    // the mask-free column chunks, then the masked ones
+                    if (pass_bytes) *pass_bytes += (double)a.g.nx * a.g.ny * a.g.nz;
+                    auto go = [&](auto mc, const int4 *list, int n) {
+                        constexpr bool M = decltype(mc)::value;
+                        if (n == 0) return;
+                        const dim3 lblock(64 * Step2Shape<L, S, M>::WAVES, 1, 1);
+                        if (a.nt)
+                            hipLaunchKernelGGL((k_step2_list<L, S, true, M>), dim3(n), lblock, 0,
+                                               a.stream, (const S *)a.src, (S *)a.dst, a.mask, a.g,
+                                               r, list, n);
+                        else
+                            hipLaunchKernelGGL((k_step2_list<L, S, false, M>), dim3(n), lblock, 0,
+                                               a.stream, (const S *)a.src, (S *)a.dst, a.mask, a.g,
+                                               r, list, n);
+                    };
+                    go(std::false_type{}, a.tasks_plain, a.n_plain);
+                    go(std::true_type{}, a.tasks_special, a.n_special);
+                } else if (a.nt) {
                     hipLaunchKernelGGL((k_step2<L, S, true>), grid, block, 0, a.stream,
                                        (const S *)a.src, (S *)a.dst, a.g, r, zc);
-                else
+                } else {
                     hipLaunchKernelGGL((k_step2<L, S, false>), grid, block, 0, a.stream,
                                        (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                }
                 launched = true;
             }
             return PTRT_OK;

@@ -1,10 +1,11 @@
 """Two steps per pass (temporal blocking through LDS: D3Q19 in FP32 and
 FP64, D2Q9 in FP32 and FP64): the kernel must give the same populations, bit for
 bit, as one step per pass, for odd and even step counts, ragged strips and
-row chunks, and through the graph-replay path of small lattices;
-ineligible configurations (other storage types and lattices, solids, nx not
-a multiple of 64 in 3D) fall back to one step per pass.  Eligible cases are
-also checked against the FP64 oracle."""
+row chunks, with solids and open boundaries, and through the graph-replay
+path of small lattices; ineligible configurations (other storage types and
+lattices, solids near most rows, nx not a multiple of 64 in 3D) fall back
+to one step per pass.  Eligible cases are also checked against the FP64
+oracle."""
 import numpy as np
 import pytest
 
@@ -289,3 +290,59 @@ def test_two_steps_per_pass_d2q9_open_floor():
     print_case("D2Q9 open x below 2^20 nodes: one step per pass")
     _, p = _run_open((1, 1000, 1000), "f64", 4, 2)
     assert p == 1
+
+
+def _d3_masks():
+    """D3Q19 solid layouts of 2^24 nodes with few near-solid column chunks
+    (where two steps per pass are used): channel walls at y = 0 and ny - 1
+    (the y seam); a cube, a band of random solids in z and a block on the
+    x seam, in a lattice whose y extent is not a multiple of 4."""
+    rng = np.random.default_rng(31)
+    out = []
+    m = np.zeros((256, 1024, 64), dtype=np.uint8)
+    m[:, 0, :] = m[:, -1, :] = 1
+    out.append(m)
+    m = np.zeros((256, 1030, 64), dtype=np.uint8)
+    m[100:104, 500:504, 20:24] = 1
+    m[30:33, 200:203] = rng.random((3, 3, 64)) < 0.2
+    m[5:9, 12:15, 0] = 1
+    m[5:9, 12:15, 63] = 1
+    out.append(m)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("case", range(2))
+def test_two_steps_per_pass_d3q19_solids_bitwise(storage, case):
+    """D3Q19 with solids: mask-free column chunks in one launch, the chunks
+    near solids (short z chunks, bounce-back in both steps) in a second;
+    7 steps (three passes and a single step), bit for bit against one step
+    per pass on every fluid node."""
+    mask = _d3_masks()[case]
+    print_case("D3Q19 with solids, steps per pass 2 vs 1", storage, mask.shape)
+    a = _run(1, mask.shape, storage, 7, 1, mask=mask, force=[1e-6, 0, 0])
+    b = _run(1, mask.shape, storage, 7, 2, mask=mask, force=[1e-6, 0, 0])
+    fluid = np.broadcast_to(mask == 0, a.shape)
+    assert np.array_equal(a[fluid], b[fluid])
+    del a, b
+
+
+def _last_pass_3d(m, st):
+    nz, ny, nx = m.shape
+    with P.Lattice(1, nx, ny, nz, 0.6, 0.25, storage=st, solid_mask=m) as G:
+        G.init_equilibrium(np.ones(m.shape), np.zeros((3,) + m.shape))
+        G.step(4)
+        return G.last_pass()
+
+
+def test_two_steps_per_pass_d3q19_solids_used_where_it_pays():
+    """From 2^24 nodes with at most 5 % of the column chunks near solids."""
+    print_case("D3Q19 with solids: last pass")
+    m = _d3_masks()[0]
+    for st in ("f32", "f64"):
+        assert _last_pass_3d(m, st) == (2, (2.0 * 19 * (4 if st == "f32" else 8) + 1) * m.size)
+    # below 2^24 nodes, or solids near many chunks: one step per pass
+    assert _last_pass_3d(m[:, :1020], "f32")[0] == 1
+    cube = np.zeros((128, 512, 256), dtype=np.uint8)
+    cube[48:80, 240:272, 112:144] = 1
+    assert _last_pass_3d(cube, "f32")[0] == 1
