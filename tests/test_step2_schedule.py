@@ -3,7 +3,7 @@ the CPU: which first-step value each second-step population reads, in
 which LDS slot of its direction class it is held, which halo a workgroup
 recomputes, and (D2Q9 with solids) where halfway bounce-back takes the
 node's own first-step value instead, on the host's split into mask-free
-chunks and shorter masked ones.  The schedule is emulated here in
+chunks and shorter masked ones (D2Q9 rows, D3Q19 column chunks).  The schedule is emulated here in
 NumPy with the oracle's collision as the per-node map, and the second
 step's pulled populations must equal the oracle's state after two steps
 (pulled = pre-collision) exactly.  CPU only: the kernels themselves are
@@ -104,6 +104,121 @@ def test_d3q19_schedule(nx, ny, nz, BY, zc):
     got = _two_step_3d(stored, e, 0.7, 0.25, BY, zc)
     assert not np.isnan(got).any()
     assert np.abs(got - ref).max() < 1e-14
+
+
+def _two_step_3d_tasks(stored, e, opp, tp, lam, tasks, solid=None):
+    """k_step2_list schedule on D3Q19: one workgroup per task (x0, y0, zs,
+    ze, masked): 64 x 4 columns, planes zs ... ze - 1; masked tasks keep two
+    slots of the e_z = -1 class and apply bounce-back in both steps."""
+    Q, nz, ny, nx = stored.shape
+    BY, AX, AY = 4, 66, 6
+    AP = AX * AY
+    m = solid if solid is not None else np.zeros((nz, ny, nx), np.uint8)
+    out = np.full(stored.shape, np.nan)
+    ex, ey, ez = (e[:, a].astype(int) for a in range(3))
+    ax = np.concatenate([np.tile(np.arange(1, 65), AY), np.zeros(AY, int), np.full(AY, AX - 1)])
+    ay = np.concatenate([np.repeat(np.arange(AY), 64), np.arange(AY), np.arange(AY)])
+    bxl = np.tile(np.arange(64), BY)
+    byl = np.repeat(np.arange(BY), 64)
+    for x0, y0, zs, ze, masked in tasks:
+        cls, slots, count, index, region, planes = _classes(e, 2, masked)
+
+        def at(c, i_idx, slot, a):
+            v = (region[c] + slot * count[c] + i_idx) * AP + a
+            assert np.all((v >= 0) & (v < planes * AP))
+            return v
+
+        lds = np.full(planes * AP, np.nan)
+        for it, k in enumerate(range(zs - 1, ze + 1)):
+            gx, gy, gz = (x0 - 1 + ax) % nx, (y0 - 1 + ay) % ny, k % nz
+            raw = np.empty((Q, len(ax)))
+            for i in range(Q):
+                sz, sy, sx = (gz - ez[i]) % nz, (gy - ey[i]) % ny, (gx - ex[i]) % nx
+                v = stored[i, sz, sy, sx].copy()
+                if masked and i:
+                    s_ = m[sz, sy, sx] != 0
+                    v[s_] = stored[opp[i], gz, gy, gx][s_]
+                raw[i] = v
+            post = _collide(O.D3Q19, raw, tp, lam)
+            for i in range(Q):
+                lds[at(cls[i], index[i], it % slots[cls[i]], ay * AX + ax)] = post[i]
+            if k < zs + 1:
+                continue
+            bz_, by_, bx_ = (k - 1) % nz, (y0 + byl) % ny, x0 + bxl
+            h = np.empty((Q, len(bxl)))
+            for i in range(Q):
+                c = cls[i]
+                v = lds[at(c, index[i], (it - c) % slots[c],
+                           (byl + 1 - ey[i]) * AX + (bxl + 1 - ex[i]))].copy()
+                if masked and i:
+                    s_ = m[(bz_ - ez[i]) % nz, (by_ - ey[i]) % ny, (bx_ - ex[i]) % nx] != 0
+                    io = opp[i]
+                    own = lds[at(cls[io], index[io], (it - 1) % slots[cls[io]],
+                                 (byl + 1) * AX + (bxl + 1))]
+                    v[s_] = own[s_]
+                h[i] = v
+            if masked:
+                h[:, m[bz_, by_, bx_] != 0] = np.nan
+            out[:, bz_, by_, bx_] = h
+    return out
+
+
+def _tasks_3d(shape, zc, zm, solid=None):
+    """(x0, y0, zs, ze, masked) as the host builds them: 64 x 4 columns,
+    chunks of zc planes; a chunk whose first-step rows y0 - 1 ... y0 + 4,
+    zs - 1 ... ze have a solid within one row is masked and split into
+    chunks of zm planes."""
+    nz, ny, nx = shape
+    near = np.zeros((nz, ny), bool)
+    if solid is not None:
+        sr = solid.any(axis=2)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                near |= np.roll(np.roll(sr, dz, 0), dy, 1)
+    out = []
+    for zs in range(0, nz, zc):
+        ze = min(zs + zc, nz)
+        for y0 in range(0, ny, 4):
+            nr = near[np.ix_([z % nz for z in range(zs - 1, ze + 1)],
+                             [y % ny for y in range(y0 - 1, y0 + 5)])].any()
+            for x0 in range(0, nx, 64):
+                if not nr:
+                    out.append((x0, y0, zs, ze, False))
+                else:
+                    out += [(x0, y0, z, min(z + zm, ze), True) for z in range(zs, ze, zm)]
+    return out
+
+
+def _masks_3d():
+    rng = np.random.default_rng(5)
+    m1 = np.zeros((6, 16, 64), np.uint8)
+    m1[:, 0, :] = m1[:, -1, :] = 1
+    m2 = np.zeros((7, 10, 64), np.uint8)
+    m2[2:4, 3:6, 10:14] = 1
+    m2[4, 7, 0] = m2[4, 7, 63] = 1
+    m3 = (rng.random((5, 12, 64)) < 0.03).astype(np.uint8)
+    # a solid one row outside the first-step rows of the chunk at y0 = 8
+    # (rows 7 ... 12) and one plane below the chunk at zs = 4 (planes 3 ... 6)
+    m4 = np.zeros((6, 16, 64), np.uint8)
+    m4[2, 6, 10:13] = 1
+    return [(m1, 3, 2), (m2, 4, 1), (m3, 5, 2), (m4, 2, 1)]
+
+
+@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("masked_everywhere", [False, True])
+def test_d3q19_schedule_solids(case, masked_everywhere):
+    """Bounce-back in both steps on the masked column chunks (shorter z
+    chunks, the e_z = -1 class with two slots); the mask-free code on the
+    others changes nothing (against every chunk masked)."""
+    mask, zc, zm = _masks_3d()[case]
+    e, _, opp = O.lattice(O.D3Q19)
+    tasks = _tasks_3d(mask.shape, zc, zm, np.ones_like(mask) if masked_everywhere else mask)
+    assert any(t[4] for t in tasks)
+    stored, ref = _start(O.D3Q19, mask.shape, 0.8, 3 / 16, solid=mask)
+    got = _two_step_3d_tasks(stored, e, opp, 0.8, 3 / 16, tasks, solid=mask)
+    fluid = np.broadcast_to(mask == 0, got.shape)
+    assert not np.isnan(got[fluid]).any()
+    assert np.abs(got[fluid] - ref[fluid]).max() < 1e-14
 
 
 def _tasks_2d(ny, nx, yc, near=None, ym=None):
