@@ -58,7 +58,11 @@
  * Errors: every int-returning call returns PTRT_OK (0) or a negative code and
  * leaves a message readable with ptrt_last_error.  A handle is not
  * thread-safe; distinct handles are independent.  Sizes are limited to
- * nx*ny*nz < 2^31 nodes per lattice.
+ * nx*ny*nz < 2^31 nodes per lattice, and the rows to Q * pitch < 2^32
+ * elements, pitch = nx rounded up to whole 128-byte lines of the storage
+ * type (the kernels form offsets inside a row tile in 32 bits):
+ * ptrt_create (checked for FP32), ptrt_set_storage and ptrt_batch_create
+ * return PTRT_EINVAL for longer rows.
  */
 #ifndef PTRT_H
 #define PTRT_H
@@ -125,7 +129,7 @@ enum ptrt_status {
     PTRT_ETAU = -2,      /* tau+ <= 1/2, Lambda <= 0, or a non-finite parameter */
     PTRT_ENOMEM = -3,    /* device allocation failed */
     PTRT_EDEVICE = -4,   /* a HIP call failed (no GPU, launch error, ...) */
-    PTRT_EDIVERGED = -5, /* diagnostics found a non-finite mass or energy */
+    PTRT_EDIVERGED = -5, /* non-finite mass, energy or populations (diagnostics, divergence check) */
     PTRT_ESTATE = -6     /* call not valid in the handle's current state */
 };
 
@@ -243,6 +247,25 @@ int ptrt_set_populations(ptrt_ctx *ctx, const double *f_in);
 
 /* Number of steps taken since the last init. */
 int ptrt_get_time(const ptrt_ctx *ctx, long long *t_out);
+
+/* Divergence detection (the stability criterion of Sec. 3.1: a run counts
+ * as stable while it stays finite).  With every > 0, ptrt_step checks the
+ * state after each step whose count t is a multiple of `every`: a kernel
+ * scans the whole population buffer for NaN or infinity and keeps, on the
+ * device, the earliest such t; the result is copied to pinned host memory
+ * behind the steps, without a wait.  A later ptrt_step that sees a recorded
+ * step returns PTRT_EDIVERGED (message with the step) and enqueues nothing.
+ * The check reads the state once (half the traffic of a step); an even
+ * `every` keeps two steps per pass.  every = 0 turns it off.  Enabling it
+ * allocates 8 bytes of device memory and 8 of pinned host memory, owned by
+ * the handle.  Resets any recorded step (waits for the handle's stream);
+ * ptrt_init_equilibrium and ptrt_set_populations reset it too. */
+int ptrt_set_divergence_check(ptrt_ctx *ctx, int every);
+
+/* Earliest checked step at which the state was not finite, or -1 if none
+ * (or the check was never enabled), after all enqueued work has finished.
+ * Synchronises the handle's stream. */
+int ptrt_divergence_step(ptrt_ctx *ctx, long long *step_out);
 
 /* Message of the last failed call on ctx; with ctx == NULL, of the last
  * failed ptrt_create on this thread.  Never NULL. */

@@ -36,49 +36,55 @@ def _load():
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        lib = ctypes.CDLL(LIB_PATH)
-        lib.ptrt_oracle_lattice.argtypes = [ctypes.c_int, _ip, _dp, _ip]
-        lib.ptrt_oracle_ghost_basis.argtypes = [ctypes.c_int, _dp, _dp]
-        lib.ptrt_oracle_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
-        lib.ptrt_oracle_collide.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp,
-                                            ctypes.c_double, ctypes.c_double, _dp]
-        lib.ptrt_oracle_collide_tau.argtypes = lib.ptrt_oracle_collide.argtypes
-        lib.ptrt_oracle_moments.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
-        lib.ptrt_oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                        _dp, _u8p, _dp, ctypes.c_int, ctypes.c_int]
-        lib.ptrt_oracle_run_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                              ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                              ctypes.c_double, _dp, _u8p, _dp, ctypes.c_int,
-                                              ctypes.c_int]
-        lib.ptrt_oracle_collide_trt.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp,
-                                                ctypes.c_double, ctypes.c_double, _dp]
-        lib.ptrt_oracle_step_sampled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                                 ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                                 _dp, _u8p, _dp, ctypes.c_int, _llp, _dp]
-        lib.ptrt_oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _u8p,
-                                                _dp, _dp]
-        lib.ptrt_oracle_collide_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
-                                                  _dp, ctypes.c_double, ctypes.c_double, _dp]
-        lib.ptrt_oracle_fifth_modes.argtypes = [ctypes.c_int, _dp]
-        lib.ptrt_oracle_run_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                           ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
-                                           ctypes.c_int, ctypes.c_int]
-        lib.ptrt_oracle_run_open.argtypes = lib.ptrt_oracle_run_ex.argtypes + [_dp]
-        lib.ptrt_oracle_apply_outlet.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                                 ctypes.c_int, _u8p, _dp, ctypes.c_double]
-        lib.ptrt_oracle_momentum_exchange.argtypes = [
-            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-            ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp, _dp, _dp]
-        lib.ptrt_oracle_phi_gradient.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                                 ctypes.c_int, _dp, _u8p, _dp, _dp]
-        lib.ptrt_oracle_collide_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                               ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
-                                               ctypes.c_double, _dp]
-        lib.ptrt_oracle_max_threads.argtypes = []
-        _lib = lib
+        _lib = bind(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def bind(lib):
+    """Declare the argument types of the oracle's C functions on a loaded
+    library (the oracle itself, or a copy built from altered source by the
+    tests that check that the pins catch planted mistakes)."""
+    lib.ptrt_oracle_lattice.argtypes = [ctypes.c_int, _ip, _dp, _ip]
+    lib.ptrt_oracle_ghost_basis.argtypes = [ctypes.c_int, _dp, _dp]
+    lib.ptrt_oracle_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+    lib.ptrt_oracle_collide.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                        ctypes.c_double, ctypes.c_double, _dp]
+    lib.ptrt_oracle_collide_tau.argtypes = lib.ptrt_oracle_collide.argtypes
+    lib.ptrt_oracle_moments.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
+    lib.ptrt_oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    _dp, _u8p, _dp, ctypes.c_int, ctypes.c_int]
+    lib.ptrt_oracle_run_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, _dp, _u8p, _dp, ctypes.c_int,
+                                          ctypes.c_int]
+    lib.ptrt_oracle_collide_trt.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                            ctypes.c_double, ctypes.c_double, _dp]
+    lib.ptrt_oracle_step_sampled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                             _dp, _u8p, _dp, ctypes.c_int, _llp, _dp]
+    lib.ptrt_oracle_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _u8p,
+                                            _dp, _dp]
+    lib.ptrt_oracle_collide_model.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                              _dp, ctypes.c_double, ctypes.c_double, _dp]
+    lib.ptrt_oracle_fifth_modes.argtypes = [ctypes.c_int, _dp]
+    lib.ptrt_oracle_run_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp,
+                                       ctypes.c_int, ctypes.c_int]
+    lib.ptrt_oracle_run_open.argtypes = lib.ptrt_oracle_run_ex.argtypes + [_dp]
+    lib.ptrt_oracle_apply_outlet.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, _u8p, _dp, ctypes.c_double]
+    lib.ptrt_oracle_momentum_exchange.argtypes = [
+        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+        ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _u8p, _dp, _dp, _dp]
+    lib.ptrt_oracle_phi_gradient.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, _dp, _u8p, _dp, _dp]
+    lib.ptrt_oracle_collide_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                           ctypes.c_double, _dp]
+    lib.ptrt_oracle_max_threads.argtypes = []
+    return lib
 
 
 def _p(a, t=_dp):
@@ -318,3 +324,63 @@ class Lattice:
         _load().ptrt_oracle_diagnostics(self.lat, self.N, _p(self.f), _p(self.g), solid,
                                         ctypes.byref(m), ctypes.byref(k))
         return m.value, k.value
+
+
+def steps_from_fields_sampled(lat, rho, u, tau_plus, Lambda, g, nodes, nsteps):
+    """Pre-collision populations after `nsteps` steps at the flat node
+    indices `nodes` of a periodic lattice without solid nodes that starts
+    from f(0) = f^eq(rho, u) (equilibrium initialisation), [len(nodes), Q].
+
+    rho [nz, ny, nx], u [D or 3, nz, ny, nx].  Each step is Eq. PTRT,
+    collide then stream: f_i(x, s) = f*_i(x - e_i, s - 1), so f(x, nsteps)
+    depends only on f(0) within nsteps nodes of x.  The equilibrium is
+    formed on that neighbourhood (Eq. feq) and collided level by level with
+    the oracle's collision, the neighbourhood shrinking by one node per
+    step; no whole-lattice state is formed, so this reaches lattices of any
+    size at a few thousand nodes.
+    """
+    e, _, _ = lattice(lat)
+    Q = e.shape[0]
+    rho = np.asarray(rho, dtype=np.float64)
+    nz, ny, nx = rho.shape
+    u = np.asarray(u, dtype=np.float64)
+    D = 2 if lat == D2Q9 else 3
+    nodes = np.asarray(nodes, dtype=np.int64).ravel()
+    z, rem = np.divmod(nodes, nx * ny)
+    y, x = np.divmod(rem, nx)
+
+    def cube(r):
+        """Offsets (dz, dy, dx) within r nodes, as an [m, 3] array, and the
+        index of an offset in it."""
+        rz = r if D == 3 else 0
+        s = 2 * r + 1
+        dz, dy, dx = np.meshgrid(np.arange(-rz, rz + 1), np.arange(-r, r + 1),
+                                 np.arange(-r, r + 1), indexing="ij")
+        off = np.stack([dz.ravel(), dy.ravel(), dx.ravel()], axis=1)
+
+        def index(o):
+            return ((o[..., 0] + rz) * s + (o[..., 1] + r)) * s + (o[..., 2] + r)
+        return off, index
+
+    # f(0) on the neighbourhood of radius nsteps
+    off, _ = cube(nsteps)
+    gz = (z[:, None] + off[None, :, 0]) % nz
+    gy = (y[:, None] + off[None, :, 1]) % ny
+    gx = (x[:, None] + off[None, :, 2]) % nx
+    u3 = np.zeros((3,) + gz.shape)
+    for a in range(min(D, u.shape[0])):
+        u3[a] = u[a][gz, gy, gx]
+    f = equilibrium(lat, rho[gz, gy, gx].ravel(),
+                    np.moveaxis(u3, 0, -1).reshape(-1, 3)).reshape(gz.shape + (Q,))
+    g3 = _g3(g)
+    for level in range(1, nsteps + 1):
+        r = nsteps - level
+        post = collide(lat, f.reshape(-1, Q), g3, tau_plus, Lambda=Lambda).reshape(f.shape)
+        _, index_prev = cube(r + 1)
+        off_r, _ = cube(r)
+        nxt = np.empty((len(nodes), off_r.shape[0], Q))
+        for i in range(Q):
+            src = off_r - np.array([e[i, 2], e[i, 1], e[i, 0]])[None, :]
+            nxt[:, :, i] = post[:, index_prev(src), i]
+        f = nxt
+    return f[:, 0, :]

@@ -148,8 +148,8 @@ inline std::vector<uint8_t> near_solid_rows(const uint8_t *mask, int nx, int ny,
 // element count of a population buffer and fills g.
 inline long long make_layout(int Q, int nx, int ny, int nz, size_t elem, Geom &g)
 {
-    const int line = (int)(128 / elem);
-    const int pitch = (nx + line - 1) / line * line;
+    const long long line = (long long)(128 / elem);
+    const int pitch = (int)(((long long)nx + line - 1) / line * line);
     int lr = 0;
     while (((long long)pitch << (lr + 1)) * (long long)elem <= 8192) ++lr;
     g.nx = nx;
@@ -162,6 +162,29 @@ inline long long make_layout(int Q, int nx, int ny, int nz, size_t elem, Geom &g
     const long long rows = (long long)ny * nz;
     const long long ntiles = (rows + (1LL << lr) - 1) >> lr;
     return ntiles * g.tile;
+}
+
+// The kernels form two parts of every population address in 32 bits: the
+// offset inside a tile (direction chunk plus row inside the tile, below
+// Q * plane elements) and the x part in bytes (below pitch * elem).  A
+// layout where either can reach 2^32 would wrap, so it is rejected here,
+// before anything is allocated or launched.
+inline int check_layout(int Q, int nx, int ny, int nz, size_t elem, std::string &msg)
+{
+    Geom g{};
+    make_layout(Q, nx, ny, nz, elem, g);
+    const double lim = 4294967296.0;
+    if ((double)g.tile >= lim) {
+        msg = "rows too long: a tile of " + std::to_string(Q) + " directions x " +
+              std::to_string(g.plane) + " elements reaches 2^32 elements (32-bit offsets)";
+        return PTRT_EINVAL;
+    }
+    if ((double)g.pitch * (double)elem >= lim) {
+        msg = "rows too long: " + std::to_string(g.pitch) + " elements of " + std::to_string(elem) +
+              " bytes reach 2^32 bytes (32-bit offsets)";
+        return PTRT_EINVAL;
+    }
+    return PTRT_OK;
 }
 
 

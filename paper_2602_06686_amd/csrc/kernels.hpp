@@ -638,4 +638,53 @@ k_finalize3(const double *__restrict__ partials, int nparts, double *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Divergence check: scan a whole population buffer (padding and solid slots
+// hold zeros) for NaN or infinity, 16 bytes per load, and record the
+// earliest step at which one was seen: bad = min(bad, t).  The exponent
+// field of a non-finite value is all ones in each storage type.
+template <class S>
+struct NonFiniteBits;
+template <>
+struct NonFiniteBits<double> {
+    using W = unsigned long long;
+    static constexpr W mask = 0x7FF0000000000000ull;
+};
+template <>
+struct NonFiniteBits<float> {
+    using W = unsigned int;
+    static constexpr W mask = 0x7F800000u;
+};
+template <>
+struct NonFiniteBits<_Float16> {
+    using W = unsigned short;
+    static constexpr W mask = 0x7C00u;
+};
+template <>
+struct NonFiniteBits<bf16_t> {
+    using W = unsigned short;
+    static constexpr W mask = 0x7F80u;
+};
+
+template <class S>
+__global__ void __launch_bounds__(256)
+k_check_finite(const uint4 *__restrict__ buf, long long nvec, long long t,
+               unsigned long long *__restrict__ bad)
+{
+    using B = NonFiniteBits<S>;
+    using W = typename B::W;
+    constexpr int per = (int)(sizeof(uint4) / sizeof(W));
+    bool found = false;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvec; v += stride) {
+        const uint4 q = buf[v];
+        W w[per];
+        __builtin_memcpy(w, &q, sizeof(q));
+#pragma unroll
+        for (int k = 0; k < per; ++k) found |= (w[k] & B::mask) == B::mask;
+    }
+    if (__any(found) && (threadIdx.x & 63) == 0)
+        atomicMin(bad, (unsigned long long)t);
+}
+
 } // namespace ptrt

@@ -389,6 +389,7 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
         const ptrt_instance_desc &d = desc[k];
         std::string msg;
         int rc = check_params(PTRT_D2Q9, d.nx, d.ny, 1, d.tau_plus, d.Lambda, d.force, msg);
+        if (rc == PTRT_OK) rc = check_layout(9, d.nx, d.ny, 1, elem, msg);
         if (rc != PTRT_OK) {
             g_batch_create_error = "instance " + std::to_string(k) + ": " + msg;
             delete b;

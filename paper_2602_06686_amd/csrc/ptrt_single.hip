@@ -63,6 +63,14 @@ struct ptrt_ctx {
     bool use_graph = false;
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // divergence check after every check_every-th step (0 = off): the
+    // earliest step at which the state held a NaN or infinity, on the
+    // device, copied to pinned host memory after each check
+    int check_every = 0;
+    unsigned long long *d_bad = nullptr, *h_bad = nullptr;
+    hipEvent_t bad_event = nullptr;
+    bool bad_pending = false;
+    long long diverged_at = -1;
     std::string err = "no error";
 };
 
@@ -459,6 +467,96 @@ int capture_graph(ptrt_ctx *c, int parity)
     return PTRT_OK;
 }
 
+constexpr unsigned long long NO_STEP = ~0ull;
+
+// Momentum exchange: per-block partials (three per 64 x 4 gather block)
+// reduced in a fixed order into out[3], copied to force_out; synchronous.
+size_t momentum_parts(const ptrt_ctx *c)
+{
+    const dim3 grid = gather_grid(c, c->nz);
+    return (size_t)grid.x * grid.y * grid.z;
+}
+
+int momentum_exchange_with(ptrt_ctx *c, double *parts, double *out, double force_out[3])
+{
+    const dim3 grid = gather_grid(c, c->nz), block(BLK_X, BLK_Y, 1);
+    const int nparts = (int)momentum_parts(c);
+    const Geom g = geom(c);
+    const void *src = c->buf[c->cur];
+    dispatch(c->lattice, c->storage, false, [&](auto lt, auto st, auto) -> int {
+        using L = typename decltype(lt)::type;
+        using S = typename decltype(st)::type;
+        with_open<L>(c, [&](auto oc) {
+            constexpr bool O = decltype(oc)::value;
+            hipLaunchKernelGGL((k_momentum_exchange<L, S, O>), grid, block, 0, c->stream,
+                               (const S *)src, c->d_mask, c->d_near, g, parts);
+        });
+        return PTRT_OK;
+    });
+    hipLaunchKernelGGL(k_finalize3<1024>, dim3(1), dim3(1024), 0, c->stream, parts, nparts, out);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(force_out, out, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PTRT_OK;
+}
+
+
+// Forget earlier check results (a new state was set); waits for the stream.
+int reset_check(ptrt_ctx *c)
+{
+    c->bad_pending = false;
+    c->diverged_at = -1;
+    if (!c->d_bad) return PTRT_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemset(c->d_bad, 0xFF, sizeof(unsigned long long)));
+    *c->h_bad = NO_STEP;
+    return PTRT_OK;
+}
+
+// Pick up the result of the latest check if its copy has arrived (no wait).
+void poll_check(ptrt_ctx *c)
+{
+    if (!c->bad_pending || hipEventQuery(c->bad_event) != hipSuccess) return;
+    c->bad_pending = false;
+    if (*c->h_bad != NO_STEP) c->diverged_at = (long long)*c->h_bad;
+}
+
+// Enqueue the check of the current state (step c->t) and the copy of its
+// result to the host.
+int launch_check(ptrt_ctx *c)
+{
+    const long long nvec = c->elems * (long long)storage_bytes(c->storage) / 16;
+    const int blocks = (int)std::min<long long>((nvec + 255) / 256, 4096);
+    dispatch_storage(c->storage, false, [&](auto st, auto) -> int {
+        using S = typename decltype(st)::type;
+        hipLaunchKernelGGL((k_check_finite<S>), dim3(blocks), dim3(256), 0, c->stream,
+                           (const uint4 *)c->buf[c->cur], nvec, c->t, c->d_bad);
+        return PTRT_OK;
+    });
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->h_bad, c->d_bad, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipEventRecord(c->bad_event, c->stream));
+    c->bad_pending = true;
+    return PTRT_OK;
+}
+
+// Enqueue n steps: graph replays where captured, else launches.
+int advance(ptrt_ctx *c, int n)
+{
+    if (c->use_graph)
+        while (n >= GRAPH_STEPS) {
+            if (!c->graph[c->cur]) {
+                int rc = capture_graph(c, c->cur);
+                if (rc != PTRT_OK) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+            n -= GRAPH_STEPS;
+        }
+    launch_steps(c, c->stream, n);
+    return PTRT_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -473,6 +571,7 @@ int ptrt_create(int lattice, int nx, int ny, int nz, double tau_plus, double Lam
     *out = nullptr;
     std::string msg;
     int rc = check_params(lattice, nx, ny, nz, tau_plus, Lambda, force, msg);
+    if (rc == PTRT_OK) rc = check_layout(lattice_q(lattice), nx, ny, nz, storage_bytes(PTRT_F32), msg);
     if (rc != PTRT_OK) {
         g_create_error = msg;
         return rc;
@@ -509,6 +608,9 @@ int ptrt_set_storage(ptrt_ctx *c, int storage)
     if (!c) return PTRT_EINVAL;
     if (storage_bytes(storage) == 0) return fail(c, PTRT_EINVAL, "unknown storage type");
     if (c->allocated) return fail(c, PTRT_ESTATE, "storage can only change before the first init");
+    std::string msg;
+    if (check_layout(c->Q, c->nx, c->ny, c->nz, storage_bytes(storage), msg) != PTRT_OK)
+        return fail(c, PTRT_EINVAL, msg);
     c->storage = storage;
     return PTRT_OK;
 }
@@ -554,31 +656,12 @@ int ptrt_momentum_exchange(ptrt_ctx *c, double force_out[3])
         return fail(c, PTRT_ESTATE, "momentum exchange needs a completed step");
     for (int a = 0; a < 3; ++a) force_out[a] = 0.0;
     if (!c->has_mask) return PTRT_OK;
-    const dim3 grid = gather_grid(c, c->nz), block(BLK_X, BLK_Y, 1);
-    const int nparts = grid.x * grid.y * grid.z;
     if (!c->d_force_parts) {
-        HIPCHK(c, hipMalloc(&c->d_force_parts, 3 * sizeof(double) * (size_t)nparts));
+        const size_t nparts = momentum_parts(c);
+        HIPCHK(c, hipMalloc(&c->d_force_parts, 3 * sizeof(double) * nparts));
         HIPCHK(c, hipMalloc(&c->d_force, 3 * sizeof(double)));
     }
-    const Geom g = geom(c);
-    const void *src = c->buf[c->cur];
-    dispatch(c->lattice, c->storage, false, [&](auto lt, auto st, auto) -> int {
-        using L = typename decltype(lt)::type;
-        using S = typename decltype(st)::type;
-        with_open<L>(c, [&](auto oc) {
-            constexpr bool O = decltype(oc)::value;
-            hipLaunchKernelGGL((k_momentum_exchange<L, S, O>), grid, block, 0, c->stream,
-                               (const S *)src, c->d_mask, c->d_near, g, c->d_force_parts);
-        });
-        return PTRT_OK;
-    });
-    hipLaunchKernelGGL(k_finalize3<1024>, dim3(1), dim3(1024), 0, c->stream, c->d_force_parts,
-                       nparts, c->d_force);
-    HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(force_out, c->d_force, 3 * sizeof(double), hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PTRT_OK;
+    return momentum_exchange_with(c, c->d_force_parts, c->d_force, force_out);
 }
 
 int ptrt_last_pass(const ptrt_ctx *c, int *steps, double *bytes)
@@ -636,7 +719,7 @@ int ptrt_init_equilibrium(ptrt_ctx *c, const double *rho, const double *u)
     if (rc != PTRT_OK) return rc;
     c->initialized = true;
     c->t = 0;
-    return PTRT_OK;
+    return reset_check(c);
 }
 
 int ptrt_set_populations(ptrt_ctx *c, const double *f)
@@ -647,7 +730,7 @@ int ptrt_set_populations(ptrt_ctx *c, const double *f)
     rc = upload_state(c, nullptr, nullptr, f);
     if (rc != PTRT_OK) return rc;
     c->initialized = true;
-    return PTRT_OK;
+    return reset_check(c);
 }
 
 int ptrt_step(ptrt_ctx *c, int n)
@@ -657,17 +740,26 @@ int ptrt_step(ptrt_ctx *c, int n)
     if (!c->initialized) return fail(c, PTRT_ESTATE, "ptrt_step before init");
     if (c->forcing == FORCE_II_G && !c->d_phi)
         return fail(c, PTRT_ESTATE, "no Phi field for the cubic correction");
-    c->t += n;
-    if (c->use_graph)
-        while (n >= GRAPH_STEPS) {
-            if (!c->graph[c->cur]) {
-                int rc = capture_graph(c, c->cur);
-                if (rc != PTRT_OK) return rc;
-            }
-            HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
-            n -= GRAPH_STEPS;
+    if (c->check_every > 0) {
+        poll_check(c);
+        if (c->diverged_at >= 0)
+            return fail(c, PTRT_EDIVERGED,
+                        "the divergence check found a non-finite population at step " +
+                            std::to_string(c->diverged_at) + "; no steps enqueued");
+    }
+    while (n > 0) {
+        int m = n;
+        if (c->check_every > 0)
+            m = (int)std::min<long long>(n, c->check_every - c->t % c->check_every);
+        int rc = advance(c, m);
+        if (rc != PTRT_OK) return rc;
+        c->t += m;
+        n -= m;
+        if (c->check_every > 0 && c->t % c->check_every == 0) {
+            rc = launch_check(c);
+            if (rc != PTRT_OK) return rc;
         }
-    launch_steps(c, c->stream, n);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return PTRT_OK;
@@ -718,6 +810,35 @@ int ptrt_diagnostics(ptrt_ctx *c, double *mass, double *ke)
     return PTRT_OK;
 }
 
+int ptrt_set_divergence_check(ptrt_ctx *c, int every)
+{
+    if (!c) return PTRT_EINVAL;
+    if (every < 0) return fail(c, PTRT_EINVAL, "the check interval must be >= 0");
+    if (every > 0 && !c->d_bad) {
+        HIPCHK(c, hipMalloc(&c->d_bad, sizeof(unsigned long long)));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_bad, sizeof(unsigned long long), hipHostMallocDefault));
+        HIPCHK(c, hipEventCreateWithFlags(&c->bad_event, hipEventDisableTiming));
+    }
+    const int rc = reset_check(c);
+    if (rc != PTRT_OK) return rc;
+    c->check_every = every;
+    return PTRT_OK;
+}
+
+int ptrt_divergence_step(ptrt_ctx *c, long long *step)
+{
+    if (!c || !step) return PTRT_EINVAL;
+    *step = -1;
+    if (!c->d_bad) return PTRT_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    unsigned long long v = NO_STEP;
+    HIPCHK(c, hipMemcpy(&v, c->d_bad, sizeof(v), hipMemcpyDeviceToHost));
+    c->bad_pending = false;
+    if (v != NO_STEP) c->diverged_at = (long long)v;
+    *step = c->diverged_at;
+    return PTRT_OK;
+}
+
 int ptrt_get_time(const ptrt_ctx *c, long long *t)
 {
     if (!c || !t) return PTRT_EINVAL;
@@ -748,6 +869,9 @@ int ptrt_destroy(ptrt_ctx *c)
     if (c->d_phi) (void)hipFree(c->d_phi);
     if (c->d_force_parts) (void)hipFree(c->d_force_parts);
     if (c->d_force) (void)hipFree(c->d_force);
+    if (c->d_bad) (void)hipFree(c->d_bad);
+    if (c->h_bad) (void)hipHostFree(c->h_bad);
+    if (c->bad_event) (void)hipEventDestroy(c->bad_event);
     delete c;
     return e == hipSuccess ? PTRT_OK : PTRT_EDEVICE;
 }

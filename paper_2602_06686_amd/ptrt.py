@@ -74,6 +74,8 @@ _SIGS = {
     "ptrt_get_populations": (ctypes.c_int, [_vp, _dp]),
     "ptrt_set_populations": (ctypes.c_int, [_vp, _dp]),
     "ptrt_get_time": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_longlong)]),
+    "ptrt_set_divergence_check": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ptrt_divergence_step": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_longlong)]),
     "ptrt_last_error": (ctypes.c_char_p, [_vp]),
     "ptrt_destroy": (ctypes.c_int, [_vp]),
     "ptrt_velocity_set": (ctypes.c_int, [ctypes.c_int, _ip, _dp]),
@@ -251,6 +253,17 @@ def ptrt_get_time(h):
     return t.value
 
 
+def ptrt_set_divergence_check(h, every):
+    return _check(_lib.ptrt_set_divergence_check(h.ptr, int(every)), h.ptr)
+
+
+def ptrt_divergence_step(h):
+    """Earliest checked step with a non-finite state, or -1."""
+    t = ctypes.c_longlong()
+    _check(_lib.ptrt_divergence_step(h.ptr, ctypes.byref(t)), h.ptr)
+    return t.value
+
+
 def ptrt_last_error(h=None):
     return _lib.ptrt_last_error(None if h is None else h.ptr).decode()
 
@@ -325,6 +338,12 @@ class Lattice:
 
     def set_populations(self, f):
         ptrt_set_populations(self.h, f)
+
+    def set_divergence_check(self, every):
+        ptrt_set_divergence_check(self.h, every)
+
+    def divergence_step(self):
+        return ptrt_divergence_step(self.h)
 
     @property
     def t(self):

@@ -105,3 +105,41 @@ def test_forcing_validation_without_device():
     finally:
         P.ptrt_destroy(h)
     assert P.FORCING == {"scheme2": 0, "scheme2+g": 1, "guo": 2}
+
+
+@pytest.mark.parametrize("lat,nx", [(0, 1 << 29), (1, 240_000_000), (2, 160_000_000)])
+def test_rows_beyond_32bit_offsets_rejected(lat, nx):
+    """Rows so long that Q * pitch reaches 2^32 elements would wrap the
+    kernels' 32-bit in-tile offsets: rejected on the host (no device use)."""
+    with pytest.raises(P.PtrtError) as ei:
+        P.ptrt_create(lat, nx, 1, 1, 0.7, 0.25)
+    assert ei.value.code == -1
+    assert "32-bit" in P.ptrt_last_error()
+    with pytest.raises(P.PtrtError) as ei:
+        P.ptrt_batch_create([{"nx": 1 << 29, "ny": 1, "tau_plus": 0.7, "Lambda": 0.25}])
+    assert ei.value.code == -1
+    assert "instance 0" in P.ptrt_batch_last_error() and "32-bit" in P.ptrt_batch_last_error()
+
+
+def test_long_rows_below_the_limit_accepted():
+    """9 * 2^28 elements per tile is below 2^32: accepted in every storage
+    type (nothing is allocated before init)."""
+    h = P.ptrt_create(0, 1 << 28, 1, 1, 0.7, 0.25)
+    try:
+        for st in (0, 2, 3, 1):
+            P.ptrt_set_storage(h, st)
+    finally:
+        P.ptrt_destroy(h)
+
+
+def test_divergence_check_arguments_without_device():
+    h = P.ptrt_create(1, 8, 8, 8, 0.7, 0.25)
+    try:
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_set_divergence_check(h, -1)
+        assert ei.value.code == -1
+        P.ptrt_set_divergence_check(h, 0)        # off: nothing to allocate
+        assert P.ptrt_divergence_step(h) == -1
+    finally:
+        P.ptrt_destroy(h)
+    assert P._lib.ptrt_divergence_step(None, None) == -1

@@ -1,10 +1,11 @@
 """GPU runs of the remaining configurations, with their errors reported.
 
 * Precision form: D3Q19 Taylor-Green vortex at 64^3 (the FP64 oracle's copy
-  of the 512^3 setup), FP32 / FP16 / BF16 storage against the oracle after
-  500 steps: relative L2 of the velocity and of the vorticity (central
-  differences).  Lambda = 1/4 as configured and 1/tau- = 1.6 (the paper's
-  stability optimum, Sec. 3.1).
+  of the 512^3 setup), FP64 / FP32 / FP16 / BF16 storage against the oracle
+  at steps 500 and 1000: relative L2 of the velocity and of the vorticity
+  (central differences).  At 1/tau- = 1.6 (the paper's stability optimum,
+  Sec. 3.1) with the accuracy bars; at the configured Lambda = 1/4 at step
+  500, reported.
 * Double shear layer at 2048^2 (Sec. 3.1 shape): one FP64 step checked
   against the oracle at sampled nodes; FP32 vs FP64 on the GPU and the
   divergence step, if any, at Re = 1e4, 1e6, 1e7 (Lambda = 1/4) and at
@@ -34,40 +35,68 @@ def _vorticity(u):
     return np.stack([d(uz, 1) - d(uy, 0), d(ux, 0) - d(uz, 2), d(uy, 2) - d(ux, 1)])
 
 
-@pytest.mark.parametrize("setting", ["Lambda=1/4", "1/tau-=1.6"])
-def test_precision_form_64cube(setting):
-    n, steps = 64, 500
-    prm = I.tgv3d_params(n)
-    tp = prm["tau_plus"]
-    lam = 0.25 if setting == "Lambda=1/4" else I.tau_minus_from_inverse(1.6, tp)
-    rho, u = I.tgv3d(n, 0.05)
+def _precision_errors(n, tp, lam, rho, u, checkpoints, storages):
+    """Relative L2 errors of velocity and vorticity of each storage type
+    against the FP64 oracle at each checkpoint step."""
     ora = O.Lattice(O.D3Q19, n, n, n, tp, lam)
     ora.init_equilibrium(rho, u)
-    ora.step(steps)
-    _, uo = ora.moments()
-    wo = _vorticity(uo)
+    ref, done = {}, 0
+    for t in checkpoints:
+        ora.step(t - done)
+        done = t
+        ref[t] = ora.moments()[1]
+    del ora
     errs = {}
-    # At 1/tau- = 1.6 the FP16 bar is the 1e-3 accuracy target.  At Lambda = 1/4
-    # (tau- = 262 here) the third-order modes are almost undamped and the
-    # FP64 run itself blows up after ~1000 steps, so low-precision rounding
-    # noise is hardly damped: those errors are reported, with loose bounds.
-    # FP32 at tau+ - 1/2 ~ 1e-3 accumulates more rounding than on the 2D
-    # vortex (whose 1e-5 FP32 bar is tested in test_gpu_parity.py).
-    bounds = {"Lambda=1/4": (("f32", 5e-5), ("f16", 0.2), ("bf16", 1.0)),
-              "1/tau-=1.6": (("f32", 2e-5), ("f16", 1e-3), ("bf16", 2e-2))}[setting]
-    for storage, bound in bounds:
-        print_case("precision form 64^3", setting, storage)
+    for storage in storages:
+        print_case("precision form", f"{n}^3", storage, checkpoints)
         with P.Lattice(1, n, n, n, tp, lam, storage=storage) as G:
             G.init_equilibrium(rho, u)
-            G.step(steps)
-            _, ug = G.moments()
-        eu = A.rel_l2(ug, uo)
-        ew = A.rel_l2(_vorticity(ug), wo)
-        errs[storage] = (eu, ew)
-        print(f"precision form {setting} {storage} 64^3 {steps} steps: "
-              f"velocity rel L2 {eu:.3e}, vorticity rel L2 {ew:.3e}", flush=True)
-        assert eu < bound and ew < 5 * bound
-    assert errs["f16"][0] < errs["bf16"][0]
+            done = 0
+            for t in checkpoints:
+                G.step(t - done)
+                done = t
+                ug = G.moments()[1]
+                errs[(storage, t)] = (A.rel_l2(ug, ref[t]),
+                                      A.rel_l2(_vorticity(ug), _vorticity(ref[t])))
+                print(f"precision form {n}^3 {storage} step {t}: velocity rel L2 "
+                      f"{errs[(storage, t)][0]:.3e}, vorticity rel L2 {errs[(storage, t)][1]:.3e}",
+                      flush=True)
+    return errs
+
+
+def test_precision_form_64cube_stable():
+    """At the paper's 1/tau- = 1.6 (Sec. 3.1): the accuracy bars at steps 500
+    and 1000 (nx = 64, so FP64 and FP32 run two steps per pass): FP64 within
+    1e-12 of the oracle, FP32 within 1e-5 and FP16 within 1e-3 in relative
+    L2 of the velocity; BF16 reported (bounded loosely)."""
+    n = 64
+    tp = I.tgv3d_params(n)["tau_plus"]
+    lam = I.tau_minus_from_inverse(1.6, tp)
+    rho, u = I.tgv3d(n, 0.05)
+    errs = _precision_errors(n, tp, lam, rho, u, (500, 1000), ("f64", "f32", "f16", "bf16"))
+    bars = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3, "bf16": 5e-2}
+    for (storage, t), (eu, ew) in errs.items():
+        assert eu < bars[storage], (storage, t, eu)
+        assert ew < 5 * bars[storage], (storage, t, ew)
+    for t in (500, 1000):
+        assert errs[("f16", t)][0] < errs[("bf16", t)][0]
+
+
+def test_precision_form_64cube_lambda_quarter():
+    """At the configured Lambda = 1/4 (tau- = 262 at this tau+) the
+    third-order modes are almost undamped (1 - 1/tau- = 0.996) and the FP64
+    run itself blows up after about 1000 steps, so rounding noise of the
+    storage is hardly damped: errors at step 500, reported with loose
+    bounds (FP32 5e-5: the reading that 1e-5 does not hold at this Lambda is
+    stated with the measured values in the design notes)."""
+    n = 64
+    tp = I.tgv3d_params(n)["tau_plus"]
+    rho, u = I.tgv3d(n, 0.05)
+    errs = _precision_errors(n, tp, 0.25, rho, u, (500,), ("f32", "f16", "bf16"))
+    bounds = {"f32": 5e-5, "f16": 0.2, "bf16": 1.0}
+    for (storage, t), (eu, ew) in errs.items():
+        assert eu < bounds[storage] and ew < 5 * bounds[storage], (storage, eu, ew)
+    assert errs[("f16", 500)][0] < errs[("bf16", 500)][0]
 
 
 def test_dsl_2048_fp64_step_sampled():
@@ -101,20 +130,24 @@ def test_dsl_2048_stability_and_fp32_error(Re, setting):
         G64.init_equilibrium(rho, u)
         G32.init_equilibrium(rho, u)
         m0, _ = G64.diagnostics()
+        # the library's divergence check every 100 steps
+        G64.set_divergence_check(100)
+        G32.set_divergence_check(100)
         t = 0
         while t < steps:
-            G64.step(chunk)
-            G32.step(chunk)
+            try:
+                G64.step(chunk)
+                G32.step(chunk)
+            except P.PtrtError as e:
+                assert e.code == -5, e
+                break
             t += chunk
-            m64, k64 = G64.diagnostics(raise_on_divergence=False)
-            m32, k32 = G32.diagnostics(raise_on_divergence=False)
-            if not (np.isfinite(m64) and np.isfinite(k64)):
-                res["diverged_fp64_by_step"] = t
-                break
-            if not (np.isfinite(m32) and np.isfinite(k32)):
-                res["diverged_fp32_by_step"] = t
-                break
-        if "diverged_fp64_by_step" not in res and "diverged_fp32_by_step" not in res:
+        for key, G in (("fp64", G64), ("fp32", G32)):
+            d = G.divergence_step()
+            if d >= 0:
+                res[f"diverged_{key}_at_step"] = d
+        if not any(k.startswith("diverged") for k in res):
+            m64, _ = G64.diagnostics()
             _, u64 = G64.moments()
             _, u32 = G32.moments()
             res["fp32_vs_fp64_velocity_rel_l2"] = A.rel_l2(u32[:2], u64[:2])
@@ -127,29 +160,77 @@ def test_dsl_2048_stability_and_fp32_error(Re, setting):
         assert res["mass_rel_change_fp64"] < 1e-10
 
 
-def test_tgv3d_256_kinetic_energy_decay():
-    print_case("3D TGV 256^3 FP32 kinetic energy")
+def test_divergence_check_reports_the_oracle_step():
+    """The library's divergence check against the oracle's divergence step:
+    the double shear layer at 128^2, Re = 1e4, Lambda = 1/4 (Sec. 3.1 shape)
+    in FP64, checked every 10 steps.  ptrt_step returns PTRT_EDIVERGED after
+    the first check that saw a non-finite population, naming the step, and
+    ptrt_divergence_step reports that step, within two check intervals of
+    the oracle's (the two agree to 1e-12 until the growth of the unstable
+    modes amplifies their different rounding).  FP32 storage is reported."""
+    from test_oracle_stability import N, RE, U0, divergence_step, dsl_lattice
+    print_case("divergence check DSL 128^2 oracle")
+    ref = divergence_step(dsl_lattice(), 2560)
+    tp = I.tau_plus_from_nu(U0 * N / RE)
+    rho, u = I.double_shear_layer(N, U0)
+    got = {}
+    for storage in ("f64", "f32"):
+        print_case("divergence check DSL 128^2", storage)
+        with P.Lattice(0, N, N, 1, tp, 0.25, storage=storage) as G:
+            G.init_equilibrium(rho, u[:2])
+            G.set_divergence_check(10)
+            err = None
+            try:
+                for _ in range(400):
+                    G.step(10)
+            except P.PtrtError as e:
+                err = e
+            got[storage] = G.divergence_step()
+        print(f"DSL 128^2 Lambda=1/4 {storage}: library divergence step {got[storage]} "
+              f"(oracle {ref})", flush=True)
+        assert err is not None and err.code == -5 and str(got[storage]) in str(err)
+    assert abs(got["f64"] - ref) <= 20
+
+
+@pytest.mark.parametrize("setting", ["Lambda=1/4", "1/tau-=1.6"])
+def test_tgv3d_256_kinetic_energy_decay(setting):
+    """3D vortex at 256^3, FP32, 5000 steps (configured length): the kinetic
+    energy from the FP64 GPU reduction every 250 steps, the divergence step
+    from the library's check (every 50 steps).  The early decay follows the
+    viscous closed form exp(-6 nu k^2 t) within 2 % (kinetic-acoustic
+    exchange at Ma ~ 0.09 keeps it from being closer).  At the configured
+    Lambda = 1/4 the run diverges; the paper's optimum 1/tau- = 1.6
+    (Sec. 3.1) is run beside it and its divergence step, if any, reported."""
+    print_case("3D TGV 256^3 FP32 kinetic energy", setting)
     n, U0 = 256, 0.05
     prm = I.tgv3d_params(n, U0)
     nu, tp = prm["nu"], prm["tau_plus"]
+    lam = 0.25 if setting == "Lambda=1/4" else I.tau_minus_from_inverse(1.6, tp)
     rho, u = I.tgv3d(n, U0)
     k = 2 * np.pi / n
-    with P.Lattice(1, n, n, n, tp, 0.25, storage="f32") as G:
+    with P.Lattice(1, n, n, n, tp, lam, storage="f32") as G:
         G.init_equilibrium(rho, u)
+        del rho, u
+        G.set_divergence_check(50)
         m0, e0 = G.diagnostics()
         series = [(0, e0)]
-        diverged = None
         for t in range(250, 5001, 250):
-            G.step(250)
+            try:
+                G.step(250)
+            except P.PtrtError as e:
+                assert e.code == -5, e
+                break
             m, e = G.diagnostics(raise_on_divergence=False)
             if not np.isfinite(e):
-                diverged = t
                 break
             series.append((t, e))
-    print("3D TGV 256^3 E(t)/E0:", [(t, round(e / e0, 5)) for t, e in series],
-          "diverged by step" if diverged else "", diverged or "", flush=True)
-    # early decay against the viscous closed form exp(-6 nu k^2 t) (loose:
-    # kinetic-acoustic exchange at Ma ~ 0.09)
+        diverged = G.divergence_step()
+    print(f"3D TGV 256^3 {setting} E(t)/E0:", [(t, round(e / e0, 5)) for t, e in series],
+          f"diverged at step {diverged}" if diverged >= 0 else "finite through 5000 steps",
+          flush=True)
     t1, e1 = series[2]
     assert abs(e1 / e0 - np.exp(-6 * nu * k * k * t1)) < 2e-2
-    assert abs(m - m0) < 1e-5 * m0 if diverged is None else True
+    if diverged < 0:
+        assert abs(m - m0) < 1e-5 * m0
+    if setting == "Lambda=1/4":
+        assert 0 < diverged <= 5000
