@@ -213,6 +213,20 @@ int ptrt_set_open_x(ptrt_ctx *ctx, double u_in, double rho_out);
  * first call allocates a small reduction buffer owned by the handle. */
 int ptrt_momentum_exchange(ptrt_ctx *ctx, double force_out[3]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * force as ptrt_momentum_exchange, from the same kernels in the same order
+ * (bit-identical results), with the per-block partials and the result in a
+ * fixed 16 MiB device array of the library instead of buffers it allocates.
+ * Calls no hipMalloc or hipFree.  The array holds 3 doubles per 64 x 4
+ * block of nodes (nx/64 x ny/4 x nz blocks, rounded up) after 256 bytes for
+ * the result: up to 699040 blocks (a 512^3 lattice needs 524288);
+ * PTRT_EINVAL for larger lattices.  Every call on a GPU uses that GPU's one
+ * array (held until the process ends), so calls that overlap on one GPU,
+ * from any handle or thread, race; each call overwrites all it reads.
+ * Synchronises the handle's stream; PTRT_ESTATE before the first step. */
+int ptrt_momentum_exchange_noalloc(ptrt_ctx *ctx, double force_out[3]);
+
 /* Stream for all later work of this handle; a hipStream_t passed as void*
  * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */
 int ptrt_set_stream(ptrt_ctx *ctx, void *hip_stream);

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,9 @@ static_assert(FORCE_II == PTRT_FORCING_SCHEME2 && FORCE_II_G == PTRT_FORCING_SCH
 static_assert(MODEL_PTRT == PTRT_MODEL_PTRT && MODEL_TRT_RLB == PTRT_MODEL_TRT_RLB &&
                   MODEL_TRT == PTRT_MODEL_TRT && MODEL_PTRT_EXACT == PTRT_MODEL_PTRT_EXACT,
               "model ids of the kernels and of the C interface");
+
+// Device scratch of ptrt_momentum_exchange_noalloc (see noalloc_scratch).
+static __device__ __align__(256) char scratch[16u << 20];
 
 namespace {
 
@@ -500,6 +504,32 @@ int momentum_exchange_with(ptrt_ctx *c, double *parts, double *out, double force
     return PTRT_OK;
 }
 
+// Fixed device scratch of ptrt_momentum_exchange_noalloc: the three result
+// values at offset 0, the per-block partials from NOALLOC_PARTS_OFFSET on.
+// In host code `scratch` only names the symbol; its device address (one per
+// GPU) comes from hipGetSymbolAddress on the first call on that GPU.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 16u << 20;
+constexpr size_t NOALLOC_PARTS_OFFSET = 256;
+static_assert(sizeof(scratch) == NOALLOC_SCRATCH_BYTES, "scratch size");
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+int noalloc_scratch(ptrt_ctx *c, char **out)
+{
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(c, PTRT_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(c, PTRT_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return PTRT_OK;
+}
 
 // Forget earlier check results (a new state was set); waits for the stream.
 int reset_check(ptrt_ctx *c)
@@ -662,6 +692,27 @@ int ptrt_momentum_exchange(ptrt_ctx *c, double force_out[3])
         HIPCHK(c, hipMalloc(&c->d_force, 3 * sizeof(double)));
     }
     return momentum_exchange_with(c, c->d_force_parts, c->d_force, force_out);
+}
+
+int ptrt_momentum_exchange_noalloc(ptrt_ctx *c, double force_out[3])
+{
+    if (!c || !force_out) return PTRT_EINVAL;
+    const size_t need = NOALLOC_PARTS_OFFSET + 3 * sizeof(double) * momentum_parts(c);
+    if (c->has_mask && need > NOALLOC_SCRATCH_BYTES)
+        return fail(c, PTRT_EINVAL,
+                    "lattice too large for the fixed scratch of ptrt_momentum_exchange_noalloc: "
+                    "needs " + std::to_string(need) + " bytes, holds " +
+                        std::to_string(NOALLOC_SCRATCH_BYTES) +
+                        " (one 64 x 4 node block per 24 bytes); use ptrt_momentum_exchange");
+    if (!c->initialized || c->t == 0)
+        return fail(c, PTRT_ESTATE, "momentum exchange needs a completed step");
+    for (int a = 0; a < 3; ++a) force_out[a] = 0.0;
+    if (!c->has_mask) return PTRT_OK;
+    char *base = nullptr;
+    const int rc = noalloc_scratch(c, &base);
+    if (rc != PTRT_OK) return rc;
+    return momentum_exchange_with(c, reinterpret_cast<double *>(base + NOALLOC_PARTS_OFFSET),
+                                  reinterpret_cast<double *>(base), force_out);
 }
 
 int ptrt_last_pass(const ptrt_ctx *c, int *steps, double *bytes)

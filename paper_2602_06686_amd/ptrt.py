@@ -66,6 +66,7 @@ _SIGS = {
     "ptrt_set_steps_per_pass": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_last_pass": (ctypes.c_int, [_vp, _ip, _dp]),
     "ptrt_momentum_exchange": (ctypes.c_int, [_vp, _dp]),
+    "ptrt_momentum_exchange_noalloc": (ctypes.c_int, [_vp, _dp]),
     "ptrt_set_stream": (ctypes.c_int, [_vp, _vp]),
     "ptrt_init_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
     "ptrt_step": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -199,6 +200,12 @@ def ptrt_set_open_x(h, u_in, rho_out):
 def ptrt_momentum_exchange(h):
     F = np.zeros(3)
     _check(_lib.ptrt_momentum_exchange(h.ptr, _ptr(F)), h.ptr)
+    return F
+
+
+def ptrt_momentum_exchange_noalloc(h):
+    F = np.zeros(3)
+    _check(_lib.ptrt_momentum_exchange_noalloc(h.ptr, _ptr(F)), h.ptr)
     return F
 
 

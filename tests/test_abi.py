@@ -143,3 +143,27 @@ def test_divergence_check_arguments_without_device():
     finally:
         P.ptrt_destroy(h)
     assert P._lib.ptrt_divergence_step(None, None) == -1
+
+
+def test_noalloc_momentum_exchange_rejects_lattices_beyond_its_scratch():
+    """The fixed scratch holds 699040 partials of 64 x 4 node blocks: a
+    lattice of 1000 x 700 blocks is rejected with a message, before any
+    device use; without a completed step a fitting lattice gets
+    PTRT_ESTATE."""
+    nx, ny = 64 * 1000, 4 * 700
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[0, 0, 0] = 1
+    h = P.ptrt_create(0, nx, ny, 1, 0.7, 0.25, solid_mask=mask)
+    try:
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_momentum_exchange_noalloc(h)
+        assert ei.value.code == -1 and "scratch" in P.ptrt_last_error(h)
+    finally:
+        P.ptrt_destroy(h)
+    h = P.ptrt_create(0, 64, 64, 1, 0.7, 0.25, solid_mask=mask[:, :64, :64])
+    try:
+        with pytest.raises(P.PtrtError) as ei:
+            P.ptrt_momentum_exchange_noalloc(h)
+        assert ei.value.code == -6
+    finally:
+        P.ptrt_destroy(h)
