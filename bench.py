@@ -62,9 +62,60 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def timed_steps(torch, stream, step_fn, steps, warmup):
+WARM_MS = 300.0  # device time of the warm-up before each timed region (default)
+WARM = [WARM_MS]  # the value in use (--warm-ms)
+
+
+def warm_for(torch, stream, step_fn, ms=None, chunk=20, max_steps=None):
+    """Run chunks of steps until `ms` of device time have passed (or
+    max_steps are done).  After a change of load the clocks settle over tens
+    of milliseconds; a fixed step count covers too little of that on large
+    lattices and too much on small ones.  Returns (steps run, ms)."""
+    ms = WARM[0] if ms is None else ms
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    done, el = 0, 0.0
+    while el < ms and (max_steps is None or done < max_steps):
+        step_fn(chunk)
+        done += chunk
+        e1.record(stream)
+        e1.synchronize()
+        el = e0.elapsed_time(e1)
+    return done, el
+
+
+WARM_MAX_STEPS = 600  # a stand-in stays well before any divergence of its flow
+
+
+def stand_in_warm(torch, stream, make, fields=(None, None), ms=None, record=None):
+    """Warm-up function: a lattice from make() (same shape, parameters and
+    kernels as the measured one) started from the same initial fields,
+    stepped for `ms` of device time (at most WARM_MAX_STEPS steps) and
+    freed, so that the measured flow is not advanced.  The same fields
+    matter: the device draws more power on the vortex's data than on a
+    state at rest, and its clock takes tens of milliseconds to settle after
+    such a change (measured: 0.58 ms per two-step pass at rest, up to 0.77
+    ms in the first passes on the vortex, 0.60 ms settled)."""
+    def fn():
+        if (WARM[0] if ms is None else ms) <= 0:
+            return
+        with make() as Lw:
+            Lw.init_equilibrium(*fields)
+            done, el = warm_for(torch, stream, Lw.step, ms, max_steps=WARM_MAX_STEPS)
+        if record is not None:
+            record["steps"], record["ms"] = done, el
+    return fn
+
+
+def timed_steps(torch, stream, step_fn, steps, warmup, warm_fn=None):
     """Run warmup steps, then time exactly `steps` steps with HIP events on
-    `stream` (bracketed by device synchronisation).  Returns (event ms, wall s)."""
+    `stream` (bracketed by device synchronisation).  warm_fn, if given, runs
+    first (a time-based warm-up on a stand-in lattice).  Returns (event ms,
+    wall s)."""
+    if warm_fn is not None:
+        warm_fn()
     if warmup:
         step_fn(warmup)
     torch.cuda.synchronize()
@@ -79,34 +130,52 @@ def timed_steps(torch, stream, step_fn, steps, warmup):
     return e0.elapsed_time(e1), wall
 
 
+def pass_accounting(res, nodes):
+    """Bandwidth figures of a timed run whose passes cover res["steps_per_pass"]
+    steps and move res["pass_bytes"] (the library's algorithmic bytes: the
+    state read once and written once per pass).  hbm_frac is the pass's own
+    bytes over its time against the 8 TB/s peak; the one-step-equivalent
+    figures (2 Q s bytes per node per step, what one step per pass would have
+    to move at this node-update rate) are named as such: with two steps per
+    pass they are not traffic and may exceed the peak."""
+    res["pass_ms"] = res["ms_per_step"] * res["steps_per_pass"]
+    res["pass_gbs"] = res["pass_bytes"] / (res["pass_ms"] * 1e-3) / 1e9
+    res["hbm_frac"] = res["pass_gbs"] / HBM_PEAK_GBS
+    res["one_step_equiv_gbs"] = res["bytes_per_node"] * nodes / (res["ms_per_step"] * 1e-3) / 1e9
+    res["mlups_over_one_step_roofline"] = res["one_step_equiv_gbs"] / HBM_PEAK_GBS
+    return res
+
+
 def bench_single(P, torch, stream, lattice, shape, storage, init, tau_plus, Lambda, steps, warmup,
-                 force=None, mask=None, diag=False, steps_per_pass=2):
+                 force=None, mask=None, diag=False, steps_per_pass=2, warm_ms=None):
     nz, ny, nx = shape
-    with P.Lattice(lattice, nx, ny, nz, tau_plus, Lambda, force=force, solid_mask=mask,
-                   storage=storage, stream=stream, steps_per_pass=steps_per_pass) as L:
+
+    def make():
+        return P.Lattice(lattice, nx, ny, nz, tau_plus, Lambda, force=force, solid_mask=mask,
+                         storage=storage, stream=stream, steps_per_pass=steps_per_pass)
+
+    warm = {}
+    warm_ms = WARM[0] if warm_ms is None else warm_ms
+    with make() as L:
         rho, u = init()
         L.init_equilibrium(rho, u)
-        del rho, u
+        warm_fn = stand_in_warm(torch, stream, make, (rho, u), warm_ms, warm) if warm_ms > 0 else None
         e0 = None
         if diag:
             m0, e0 = L.diagnostics(raise_on_divergence=False)
-        ms, wall = timed_steps(torch, stream, L.step, steps, warmup)
+        ms, wall = timed_steps(torch, stream, L.step, steps, warmup, warm_fn)
+        del rho, u, warm_fn
         nodes = nx * ny * nz
         res = {
             "shape": [nx, ny, nz], "storage": storage, "steps": steps, "warmup": warmup,
+            "warm_up_stand_in": warm,
             "ms_per_step": ms / steps, "mlups": nodes * steps / (ms * 1e-3) / 1e6,
             "wall_mlups": nodes * steps / wall / 1e6,
             "bytes_per_node": L.bytes_per_node,
         }
-        # one-step accounting: 2 Q s bytes per node per step
-        res["achieved_gbs"] = res["bytes_per_node"] * nodes / (res["ms_per_step"] * 1e-3) / 1e9
-        res["hbm_frac"] = res["achieved_gbs"] / HBM_PEAK_GBS
         # the kernel pass actually run (two steps per pass where allowed)
-        pass_steps, pass_bytes = L.last_pass()
-        res["steps_per_pass"] = pass_steps
-        res["pass_bytes"] = pass_bytes
-        res["pass_ms"] = res["ms_per_step"] * pass_steps
-        res["pass_gbs"] = pass_bytes / (res["pass_ms"] * 1e-3) / 1e9
+        res["steps_per_pass"], res["pass_bytes"] = L.last_pass()
+        pass_accounting(res, nodes)
         if diag:
             m1, e1 = L.diagnostics(raise_on_divergence=False)
             res["mass_rel_change"] = abs(m1 - m0) / m0
@@ -161,13 +230,18 @@ def form_batch(P, torch, stream, steps, warmup):
         P.ptrt_batch_set_stream(b, stream)
         # tile plan of the one-step launches (odd steps, one step per pass)
         plan = P.ptrt_batch_autotune(b)
+        plan2 = P.ptrt_batch_get_plan2(b)
         nodes = P.ptrt_batch_nodes(b)
         bps = P.ptrt_batch_bytes_per_step(b)
-        # two steps per pass (the default), then one step per pass
-        ms_f, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step(b, k), steps, warmup)
+        # two steps per pass (the default), then one step per pass; the
+        # batch's flows are steady or creeping, so it warms up on itself
+        step = lambda k: P.ptrt_batch_step(b, k)  # noqa: E731
+        ms_f, _ = timed_steps(torch, stream, step, steps, warmup,
+                              lambda: warm_for(torch, stream, step))
         spp, pass_bytes = P.ptrt_batch_last_pass(b)
         P.ptrt_batch_set_steps_per_pass(b, 1)
-        ms_1, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step(b, k), steps, warmup)
+        ms_1, _ = timed_steps(torch, stream, step, steps, warmup,
+                              lambda: warm_for(torch, stream, step))
         P.ptrt_batch_set_steps_per_pass(b, 2)
         sep_steps = max(10, steps // 10)
         ms_s, _ = timed_steps(torch, stream, lambda k: P.ptrt_batch_step_separate(b, k),
@@ -182,15 +256,19 @@ def form_batch(P, torch, stream, steps, warmup):
                     "256 force-driven channels + 256 periodic boxes with a square obstacle, per-instance tau+, Lambda=3/16",
         "instances": len(specs), "nodes": nodes, "fluid_nodes": fluid,
         "plan": {"tile_x": plan[0], "tile_y": plan[1], "blocks": plan[2], "xcd_order": plan[3]},
+        "plan2": dict(zip(("rows", "masked_rows", "waves", "blocks", "concurrent"), plan2)),
         "steps": steps, "ms_per_step": mf,
         "mlups": nodes / (mf * 1e-3) / 1e6, "mflups": fluid / (mf * 1e-3) / 1e6,
-        # one-step accounting (2 Q s + 1 bytes per node per step)
-        "achieved_gbs": bps / (mf * 1e-3) / 1e9, "hbm_frac": bps / (mf * 1e-3) / 1e9 / HBM_PEAK_GBS,
         # the pass actually run: two steps per pass move the bytes of one step
         "steps_per_pass": spp, "pass_bytes": pass_bytes, "pass_ms": mf * spp,
         "pass_gbs": pass_bytes / (mf * spp * 1e-3) / 1e9,
+        "hbm_frac": pass_bytes / (mf * spp * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        # what one step per pass would have to move at this rate (2 Q s + 1
+        # bytes per node per step): not traffic, may exceed the peak
+        "one_step_equiv_gbs": bps / (mf * 1e-3) / 1e9,
+        "mlups_over_one_step_roofline": bps / (mf * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "one_step_per_pass": {"ms_per_step": m1, "mlups": nodes / (m1 * 1e-3) / 1e6,
-                              "achieved_gbs": bps / (m1 * 1e-3) / 1e9,
+                              "pass_gbs": bps / (m1 * 1e-3) / 1e9,
                               "hbm_frac": bps / (m1 * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "separate_launches": {"steps": sep_steps, "ms_per_step": ms_s / sep_steps,
                               "mlups": nodes / (ms_s / sep_steps * 1e-3) / 1e6},
@@ -217,10 +295,13 @@ def form_models(P, torch, stream, steps, warmup):
         res = {}
         for model in ("ptrt", "trt-rlb", "trt"):
             # one step per pass for every model: a kernel-to-kernel comparison
-            with P.Lattice(lat, nx, ny, nz, tp, 0.25, storage="f32", stream=stream, model=model,
-                           steps_per_pass=1) as L:
+            def make():
+                return P.Lattice(lat, nx, ny, nz, tp, 0.25, storage="f32", stream=stream,
+                                 model=model, steps_per_pass=1)
+            with make() as L:
                 L.init_equilibrium(rho, u)
-                ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+                ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
+                                    stand_in_warm(torch, stream, make, (rho, u)))
                 res[model] = {"ms_per_step": ms / steps, "mlups": nx * ny * nz * steps / (ms * 1e-3) / 1e6}
         res["trt_rlb_time_over_ptrt"] = res["trt-rlb"]["ms_per_step"] / res["ptrt"]["ms_per_step"]
         res["trt_time_over_ptrt"] = res["trt"]["ms_per_step"] / res["ptrt"]["ms_per_step"]
@@ -240,10 +321,13 @@ def form_d3q27(P, torch, stream, steps, warmup):
     out = {"workload": "D3Q27 256^3 periodic 3D Taylor-Green vortex (U0=0.05, Re=1600, 1/tau-=1.6)"}
     for storage, model in (("f32", "ptrt"), ("f16", "ptrt"), ("f32", "ptrt-exact"),
                            ("f32", "trt-rlb"), ("f32", "trt")):
-        with P.Lattice(P.PTRT_D3Q27, n, n, n, tp, lam, storage=storage, stream=stream,
-                       model=model) as L:
+        def make():
+            return P.Lattice(P.PTRT_D3Q27, n, n, n, tp, lam, storage=storage, stream=stream,
+                             model=model)
+        with make() as L:
             L.init_equilibrium(rho, u)
-            ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+            ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
+                                stand_in_warm(torch, stream, make, (rho, u)))
             bpn = L.bytes_per_node
         mps = ms / steps
         gbs = bpn * n ** 3 / (mps * 1e-3) / 1e9
@@ -276,10 +360,13 @@ def form_forcing(P, torch, stream, steps, warmup):
         rho, u = init()
         res = {}
         for forcing in ("scheme2", "scheme2+g", "guo"):
-            with P.Lattice(lat, nx, ny, nz, tp, 0.25, force=[1e-6, 0, 0], storage="f32",
-                           stream=stream, forcing=forcing, steps_per_pass=1) as L:
+            def make():
+                return P.Lattice(lat, nx, ny, nz, tp, 0.25, force=[1e-6, 0, 0], storage="f32",
+                           stream=stream, forcing=forcing, steps_per_pass=1)
+            with make() as L:
                 L.init_equilibrium(rho, u)
-                ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+                ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
+                                    stand_in_warm(torch, stream, make, (rho, u)))
             mps = ms / steps
             alg = 2 * Q * 4 + (Q * 4 + 2 * D * 4 if forcing == "scheme2+g" else 0)
             res[forcing] = {"ms_per_step": mps, "mlups": nodes / (mps * 1e-3) / 1e6,
@@ -333,10 +420,13 @@ def form_cylinder(P, torch, stream, steps, warmup):
     out = {"workload": "D2Q9 P-TRT square cylinder 1050^2 (D=21, L=50D, Re=0.1, Ma=0.1, "
                        "velocity inlet + Zou-He outlet, Lambda=3/16)"}
     for storage in ("f64", "f32"):
-        with P.Lattice(0, n, n, 1, tp, 3 / 16, solid_mask=mask, storage=storage, stream=stream,
-                       open_x=(uc, 1.0)) as L:
+        def make():
+            return P.Lattice(0, n, n, 1, tp, 3 / 16, solid_mask=mask, storage=storage,
+                             stream=stream, open_x=(uc, 1.0))
+        with make() as L:
             L.init_equilibrium(None, u)
-            ms, _ = timed_steps(torch, stream, L.step, steps, warmup)
+            ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
+                                stand_in_warm(torch, stream, make, (None, u)))
             spp = L.last_pass()[0]
             t0 = time.perf_counter()
             for _ in range(10):
@@ -431,6 +521,9 @@ def main():
                          "d3q27, forcing, channel, cylinder, tgv64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--warm-ms", type=float, default=WARM_MS,
+                    help="device time of the warm-up before each timed region (0: none; "
+                         "for counter collection, where every launch is profiled)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -444,6 +537,7 @@ def main():
     stream = torch.cuda.Stream()
     K, W = args.steps, args.warmup
     only = args.only
+    WARM[0] = args.warm_ms
 
     if args.copy_calibration:
         log("copy calibration", copy_calibration(torch, stream))

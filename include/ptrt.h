@@ -336,11 +336,37 @@ int ptrt_batch_init_equilibrium(ptrt_batch *b, int instance, const double *rho,
  * Rebuilds the tile table and drops any captured graph. */
 int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int xcd_order);
 
-/* Time the candidate plans on the device and keep the fastest; writes the
- * chosen plan if the pointers are not NULL.  The trial steps run on the
- * current state, which is saved beforehand and restored afterwards, so the
- * batch is left as it was.  Needs one extra state-sized device buffer for
- * the duration of the call.  Synchronous. */
+/* Two-step plan of ptrt_batch_step (steps per pass 2, FP32 / FP64 storage;
+ * PTRT_ESTATE for FP16 / BF16, which have no two-step pass): the task
+ * table cuts every instance into strips of 62 columns and chunks of `rows`
+ * rows (1 ... 64); a chunk with a solid within one row of its rows takes the
+ * masked code, its rows in chunks of `masked_rows` (1 ... 64).  One wave
+ * runs one task; `waves` (2, 4 or 8) waves per workgroup; `blocks` = 0
+ * launches one wave per task, else `blocks` workgroups whose waves take
+ * every (blocks x waves)-th task (persistent).  The tasks without solids
+ * near and the masked ones are two launches; `concurrent` != 0 puts the
+ * masked launch on a second stream of the batch beside the other (two
+ * branches of the captured graph) instead of after it.  Every plan
+ * computes the same values bit for bit.  Rebuilds the task table and drops
+ * captured graphs; waits for the batch's stream. */
+int ptrt_batch_set_plan2(ptrt_batch *b, int rows, int masked_rows, int waves, int blocks,
+                         int concurrent);
+
+/* The current two-step plan: plan_out[5] = {rows, masked_rows, waves,
+ * blocks, concurrent} as for ptrt_batch_set_plan2. */
+int ptrt_batch_get_plan2(const ptrt_batch *b, int plan_out[5]);
+
+/* Time candidate plans on the device and keep the fastest.  The one-step
+ * tile plans (10 tile shapes x grids 0, 2048, 4096 x table or XCD order)
+ * are written to the pointers if not NULL.  With FP32 / FP64 storage the
+ * two-step plan is searched as well (rows 1, 2, 3, 5, 7 x masked rows 1,
+ * 2, 3 and, above 3, = rows x waves 2, 4, 8 x one wave per task or the
+ * resident grid x masked launch after or beside the other, each timed over
+ * ten passes, the five fastest again three times, the best median kept;
+ * read it with ptrt_batch_get_plan2).  The trial steps run on the current
+ * state, which is saved beforehand and restored afterwards, so the batch
+ * is left as it was.  Needs one extra state-sized device buffer for the
+ * duration of the call.  Synchronous. */
 int ptrt_batch_autotune(ptrt_batch *b, int *tile_x, int *tile_y, int *blocks, int *xcd_order);
 
 /* Enqueue n steps over every instance, replayed from captured HIP graphs
@@ -353,10 +379,10 @@ int ptrt_batch_step(ptrt_batch *b, int n);
  * ptrt_set_steps_per_pass (first step kept in LDS) over a task table of
  * (instance, 62-column strip, chunk of rows): one launch for the chunks
  * with no solid within one row and one for the others (halfway
- * bounce-back); FP16 / BF16 storage and an odd last step take one step per
- * pass.  Results are bit-identical either way.  The tile plan (set_plan,
- * autotune) applies to the one-step launches.  Waits for the batch's
- * stream. */
+ * bounce-back), as ptrt_batch_set_plan2 describes; FP16 / BF16 storage and
+ * an odd last step take one step per pass.  Results are bit-identical
+ * either way.  The tile plan (set_plan) applies to the one-step launches.
+ * Waits for the batch's stream. */
 int ptrt_batch_set_steps_per_pass(ptrt_batch *b, int steps);
 
 /* The most recent pass enqueued by ptrt_batch_step: *steps = the steps it

@@ -83,7 +83,9 @@ k_batch_step(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__re
 // Two steps per pass: wave task t is tasks[t] = {instance, x0, ys, ye}, a
 // strip of columns x0 ... x0 + BX - 1 and rows ys ... ye - 1 of the
 // instance; MASK as in step2_2d_task (tasks with no solid within one row of
-// rows ys - 1 ... ye run with MASK = false).
+// rows ys - 1 ... ye run with MASK = false).  Wave w of workgroup g takes
+// tasks g NW + w, g NW + w + G NW, ... (G workgroups): one task per wave
+// when G NW covers the table, else a persistent grid.
 template <class S, bool NT, int NW, bool MASK>
 __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(8, 8)))
@@ -96,12 +98,13 @@ k_batch_step2(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
     int wg, unused_y, unused_z;
     xcd_block(wg, unused_y, unused_z);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int t = wg * NW + w;
-    if (t >= ntasks) return;
-    const int4 tk = tasks[t];
-    const BInst<typename Codec<S>::compute> p = inst[tk.x];
-    step2_2d_task<S, NT, MASK>(src + p.off, dst + p.off, mask + p.moff, p.g, p.r,
-                               lds_all + w * (SH::K::planes * SH::W), tk.y, tk.z, tk.w);
+    const int stride = (int)gridDim.x * NW;
+    for (int t = wg * NW + w; t < ntasks; t += stride) {
+        const int4 tk = tasks[t];
+        const BInst<typename Codec<S>::compute> p = inst[tk.x];
+        step2_2d_task<S, NT, MASK>(src + p.off, dst + p.off, mask + p.moff, p.g, p.r,
+                                   lds_all + w * (SH::K::planes * SH::W), tk.y, tk.z, tk.w);
+    }
 }
 
 thread_local std::string g_batch_create_error = "no error";
@@ -137,11 +140,17 @@ struct ptrt_batch {
     hipStream_t stream = nullptr, capture_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_flip[2] = {0, 0}; // buffer parity change of a replay
-    // two steps per pass: steps per pass asked for, rows per chunk, the
-    // task table (tasks without solids near, then the others), stores
-    int spp = 2, yc2 = 0;
+    // two steps per pass: steps per pass asked for; the plan (rows per
+    // chunk of the tasks without solids near, rows per chunk of the masked
+    // ones, waves per workgroup, workgroups (0 = one wave per task), the
+    // masked launch on a second stream); the task table (tasks without
+    // solids near, then the others); stores
+    int spp = 2, yc2 = 0, ym2 = 0, nw2 = 4, blocks2 = 0, conc2 = 0;
+    std::vector<uint8_t> h_near;
     int4 *d_tasks2 = nullptr;
     int n_plain2 = 0, n_masked2 = 0;
+    hipStream_t side_stream = nullptr;
+    hipEvent_t fork_event = nullptr, join_event = nullptr;
     bool nt = false;
     int last_steps = 0;
     std::string err = "no error";
@@ -255,7 +264,11 @@ int launch_fused_any(ptrt_batch *b, hipStream_t s)
 
 bool two_step(const ptrt_batch *b) { return b->spp == 2 && b->d_tasks2 != nullptr; }
 
-// One pass of two steps: the tasks without solids near, then the others.
+// One pass of two steps: the tasks without solids near and the others, in
+// two launches, one after the other on s, or (conc2) the masked ones on a
+// second stream forked from s and joined back (in a captured graph: two
+// branches), so that they overlap with the rest.  The two launches read the
+// same state and write disjoint nodes.
 void launch_pass2_any(ptrt_batch *b, hipStream_t s)
 {
     b->last_steps = 2;
@@ -263,22 +276,40 @@ void launch_pass2_any(ptrt_batch *b, hipStream_t s)
         using S = typename decltype(st)::type;
         using C = typename Codec<S>::compute;
         if constexpr (sizeof(S) != 2) { // FP16 / BF16: no task table
-            constexpr int NW = Step2Shape2D<S>::NW;
-            auto go = [&](auto mc, const int4 *list, int n) {
+            auto go = [&](auto mc, const int4 *list, int n, hipStream_t q) {
                 constexpr bool M = decltype(mc)::value;
                 if (n == 0) return;
-                const dim3 grid((n + NW - 1) / NW), block(64 * NW);
                 const S *src = (const S *)b->buf[b->cur];
                 S *dst = (S *)b->buf[b->cur ^ 1];
-                if (b->nt)
-                    hipLaunchKernelGGL((k_batch_step2<S, true, NW, M>), grid, block, 0, s, src, dst,
-                                       b->d_mask, (const BInst<C> *)b->d_inst, list, n);
-                else
-                    hipLaunchKernelGGL((k_batch_step2<S, false, NW, M>), grid, block, 0, s, src, dst,
-                                       b->d_mask, (const BInst<C> *)b->d_inst, list, n);
+                auto launch = [&](auto nwc) {
+                    constexpr int NW = decltype(nwc)::value;
+                    int grid = (n + NW - 1) / NW;
+                    if (b->blocks2 > 0) grid = std::min(grid, b->blocks2);
+                    if (b->nt)
+                        hipLaunchKernelGGL((k_batch_step2<S, true, NW, M>), dim3(grid),
+                                           dim3(64 * NW), 0, q, src, dst, b->d_mask,
+                                           (const BInst<C> *)b->d_inst, list, n);
+                    else
+                        hipLaunchKernelGGL((k_batch_step2<S, false, NW, M>), dim3(grid),
+                                           dim3(64 * NW), 0, q, src, dst, b->d_mask,
+                                           (const BInst<C> *)b->d_inst, list, n);
+                };
+                if (b->nw2 == 2) launch(std::integral_constant<int, 2>{});
+                else if (b->nw2 == 8) launch(std::integral_constant<int, 8>{});
+                else launch(std::integral_constant<int, 4>{});
             };
-            go(std::false_type{}, b->d_tasks2, b->n_plain2);
-            go(std::true_type{}, b->d_tasks2 + b->n_plain2, b->n_masked2);
+            const int4 *plain = b->d_tasks2, *masked = b->d_tasks2 + b->n_plain2;
+            if (b->conc2 && b->n_plain2 > 0 && b->n_masked2 > 0) {
+                (void)hipEventRecord(b->fork_event, s);
+                (void)hipStreamWaitEvent(b->side_stream, b->fork_event, 0);
+                go(std::true_type{}, masked, b->n_masked2, b->side_stream);
+                go(std::false_type{}, plain, b->n_plain2, s);
+                (void)hipEventRecord(b->join_event, b->side_stream);
+                (void)hipStreamWaitEvent(s, b->join_event, 0);
+            } else {
+                go(std::false_type{}, plain, b->n_plain2, s);
+                go(std::true_type{}, masked, b->n_masked2, s);
+            }
         }
         return PTRT_OK;
     });
@@ -294,21 +325,31 @@ void advance(ptrt_batch *b, hipStream_t s, int n)
     for (; n > 0; --n) launch_fused_any(b, s);
 }
 
-// The two-step task table (FP32 / FP64): per instance, strips of BX
-// columns (the last may be partial) times chunks of yc2 rows (the last may
-// be partial), a chunk taking the masked code when one of its rows ys - 1
-// ... ye has a solid within one row (near, per instance at noff).
-int build_tasks2(ptrt_batch *b, const std::vector<uint8_t> &near)
+// Rows per chunk of the two-step tasks by default: the single-lattice rule,
+// at most 3 rows (on the 512-lattice benchmark batch, 38M nodes, 3 rows
+// measured best with the masked chunks as long as the others, FP32 and
+// FP64, with or without solids: FP32 GLUPS for 1, 2, 3, 4, 5, 7, 9, 12
+// rows: 92.5, 85.9, 95.0, 92.5, 93.1, 90.1, 86.4, 83.3; one step per pass
+// 81.1).  ptrt_batch_autotune searches the plan around it.
+int default_rows2(const ptrt_batch *b)
 {
-    if (b->storage != PTRT_F32 && b->storage != PTRT_F64) return PTRT_OK;
     constexpr int BX = Step2Shape2D<float>::BX;
     long long strip_rows = 0;
     for (const HostInst &h : b->inst) strip_rows += (long long)((h.nx + BX - 1) / BX) * h.ny;
-    // the single-lattice rule, at most 3 rows: on the 512-lattice benchmark
-    // batch (38M nodes) 3 rows measured best, FP32 and FP64, with or
-    // without solids (FP32 GLUPS for 1, 2, 3, 4, 5, 7, 9, 12 rows: 92.5,
-    // 85.9, 95.0, 92.5, 93.1, 90.1, 86.4, 83.3; one step per pass 81.1)
-    b->yc2 = std::min(3, step2_2d_rows_for(b->storage, strip_rows, b->total_nodes));
+    return std::min(3, step2_2d_rows_for(b->storage, strip_rows, b->total_nodes));
+}
+
+// The two-step task table (FP32 / FP64): per instance, strips of BX
+// columns (the last may be partial) times chunks of yc2 rows (the last may
+// be partial); a chunk with a solid within one row of its rows ys - 1 ...
+// ye (near, per instance at noff) takes the masked code, its rows split
+// into chunks of ym2 rows.
+int build_tasks2(ptrt_batch *b)
+{
+    if (b->storage != PTRT_F32 && b->storage != PTRT_F64) return PTRT_OK;
+    constexpr int BX = Step2Shape2D<float>::BX;
+    if (b->yc2 <= 0) b->yc2 = default_rows2(b);
+    if (b->ym2 <= 0) b->ym2 = b->yc2;
     std::vector<int4> plain, masked;
     for (int k = 0; k < b->count; ++k) {
         const HostInst &h = b->inst[k];
@@ -317,19 +358,27 @@ int build_tasks2(ptrt_batch *b, const std::vector<uint8_t> &near)
             const int ye = std::min(ys + b->yc2, h.ny);
             bool nr = false;
             for (int y = ys - 1; y <= ye && !nr; ++y)
-                nr = near[(size_t)(h.noff + ((y % h.ny) + h.ny) % h.ny)] != 0;
-            for (int bx = 0; bx < strips; ++bx)
-                (nr ? masked : plain).push_back(make_int4(k, bx * BX, ys, ye));
+                nr = b->h_near[(size_t)(h.noff + ((y % h.ny) + h.ny) % h.ny)] != 0;
+            if (!nr) {
+                for (int bx = 0; bx < strips; ++bx) plain.push_back(make_int4(k, bx * BX, ys, ye));
+            } else {
+                for (int y = ys; y < ye; y += b->ym2)
+                    for (int bx = 0; bx < strips; ++bx)
+                        masked.push_back(make_int4(k, bx * BX, y, std::min(y + b->ym2, ye)));
+            }
         }
     }
     b->n_plain2 = (int)plain.size();
     b->n_masked2 = (int)masked.size();
     plain.insert(plain.end(), masked.begin(), masked.end());
+    if (b->d_tasks2) (void)hipFree(b->d_tasks2);
+    b->d_tasks2 = nullptr;
     BHIPCHK(b, hipMalloc(&b->d_tasks2, sizeof(int4) * plain.size()));
     BHIPCHK(b, hipMemcpy(b->d_tasks2, plain.data(), sizeof(int4) * plain.size(), hipMemcpyHostToDevice));
     // non-temporal stores once the two state buffers exceed the 256 MB
     // last-level cache (as for a single lattice)
     b->nt = 2.0 * (double)b->total_elems * (double)storage_bytes(b->storage) > 256.0 * 1024 * 1024;
+    drop_graphs(b);
     return PTRT_OK;
 }
 
@@ -360,6 +409,114 @@ int check_instance(ptrt_batch *b, int k)
     if (!b) return PTRT_EINVAL;
     if (k < 0 || k >= b->count) return bfail(b, PTRT_EINVAL, "instance index out of range");
     return PTRT_OK;
+}
+
+// Workgroups of the two-step kernel (mask-free variant) that the device
+// holds at once with nw waves each: the persistent grid of a plan.
+int resident_blocks2(const ptrt_batch *b, int nw)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || cus <= 0) return 0;
+    dispatch(PTRT_D2Q9, b->storage, false, [&](auto, auto st, auto) -> int {
+        using S = typename decltype(st)::type;
+        if constexpr (sizeof(S) != 2) {
+            auto q = [&](auto nwc) {
+                constexpr int NW = decltype(nwc)::value;
+                (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void *>(&k_batch_step2<S, true, NW, false>),
+                    64 * NW, 0);
+            };
+            if (nw == 2) q(std::integral_constant<int, 2>{});
+            else if (nw == 8) q(std::integral_constant<int, 8>{});
+            else q(std::integral_constant<int, 4>{});
+        }
+        return PTRT_OK;
+    });
+    return per_cu > 0 ? per_cu * cus : 0;
+}
+
+// Device time of `passes` two-step passes after two untimed ones (ms).
+float time_passes2(ptrt_batch *b, hipEvent_t e0, hipEvent_t e1, int passes)
+{
+    for (int k = 0; k < 2; ++k) launch_pass2_any(b, b->stream);
+    (void)hipEventRecord(e0, b->stream);
+    for (int k = 0; k < passes; ++k) launch_pass2_any(b, b->stream);
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.0f;
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0f;
+    return ms;
+}
+
+// Search the two-step plan on the current state (the caller saves and
+// restores it): every combination of rows {1, 2, 3, 5, 7}, masked rows
+// {1, 2, 3, rows}, waves {2, 4, 8}, one wave per task or the resident grid,
+// masked launch after or beside the others; each timed over 10 passes, the
+// five fastest timed again three times and the best median kept.
+int autotune2(ptrt_batch *b, hipEvent_t e0, hipEvent_t e1)
+{
+    struct Plan {
+        int yc, ym, nw, blocks, conc;
+        float ms;
+    };
+    std::vector<Plan> tried;
+    static const int rows[] = {1, 2, 3, 5, 7};
+    static const int nws[] = {2, 4, 8};
+    for (int yc : rows) {
+        std::vector<int> yms = {1, 2, 3};
+        if (yc > 3) yms.push_back(yc);
+        for (int ym : yms) {
+            b->yc2 = yc;
+            b->ym2 = ym;
+            int rc = build_tasks2(b);
+            if (rc != PTRT_OK) return rc;
+            for (int nw : nws)
+                for (int pers = 0; pers < 2; ++pers)
+                    for (int conc = 0; conc < 2; ++conc) {
+                        if (conc && b->n_masked2 == 0) continue;
+                        b->nw2 = nw;
+                        b->blocks2 = pers ? resident_blocks2(b, nw) : 0;
+                        if (pers && b->blocks2 == 0) continue;
+                        b->conc2 = conc;
+                        const float ms = time_passes2(b, e0, e1, 10);
+                        if (ms < 0) return bfail(b, PTRT_EDEVICE, "two-step autotune timing failed");
+                        tried.push_back({yc, ym, nw, b->blocks2, conc, ms});
+                    }
+        }
+    }
+    if (tried.empty()) return PTRT_OK;
+    std::sort(tried.begin(), tried.end(), [](const Plan &x, const Plan &y) { return x.ms < y.ms; });
+    const size_t top = std::min<size_t>(5, tried.size());
+    Plan best = tried[0];
+    float best_med = 1e30f;
+    for (size_t i = 0; i < top; ++i) {
+        const Plan &pl = tried[i];
+        b->yc2 = pl.yc;
+        b->ym2 = pl.ym;
+        int rc = build_tasks2(b);
+        if (rc != PTRT_OK) return rc;
+        b->nw2 = pl.nw;
+        b->blocks2 = pl.blocks;
+        b->conc2 = pl.conc;
+        float t[3];
+        for (float &x : t) {
+            x = time_passes2(b, e0, e1, 10);
+            if (x < 0) return bfail(b, PTRT_EDEVICE, "two-step autotune timing failed");
+        }
+        std::sort(t, t + 3);
+        if (t[1] < best_med) {
+            best_med = t[1];
+            best = pl;
+        }
+    }
+    b->yc2 = best.yc;
+    b->ym2 = best.ym;
+    b->nw2 = best.nw;
+    b->blocks2 = best.blocks;
+    b->conc2 = best.conc;
+    return build_tasks2(b);
 }
 
 } // namespace
@@ -470,7 +627,12 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
     if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(PTRT_EDEVICE, "capture stream");
     if (build_tiles(b) != PTRT_OK) return cleanup(PTRT_EDEVICE, b->err);
-    if (build_tasks2(b, near) != PTRT_OK) return cleanup(PTRT_EDEVICE, b->err);
+    if (hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join_event, hipEventDisableTiming) != hipSuccess)
+        return cleanup(PTRT_EDEVICE, "side stream / events");
+    b->h_near = std::move(near);
+    if (build_tasks2(b) != PTRT_OK) return cleanup(PTRT_EDEVICE, b->err);
     for (int k = 0; k < count; ++k) {
         rc = ptrt_batch_init_equilibrium(b, k, nullptr, nullptr);
         if (rc != PTRT_OK) return cleanup(rc, b->err);
@@ -597,6 +759,35 @@ int ptrt_batch_step_separate(ptrt_batch *b, int n)
     return PTRT_OK;
 }
 
+int ptrt_batch_set_plan2(ptrt_batch *b, int rows, int masked_rows, int waves, int blocks,
+                         int concurrent)
+{
+    if (!b) return PTRT_EINVAL;
+    if (rows < 1 || rows > 64 || masked_rows < 1 || masked_rows > 64 ||
+        (waves != 2 && waves != 4 && waves != 8) || blocks < 0)
+        return bfail(b, PTRT_EINVAL, "invalid two-step plan");
+    if (b->storage != PTRT_F32 && b->storage != PTRT_F64)
+        return bfail(b, PTRT_ESTATE, "the two-step pass runs in FP32 and FP64 storage only");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->yc2 = rows;
+    b->ym2 = masked_rows;
+    b->nw2 = waves;
+    b->blocks2 = blocks;
+    b->conc2 = concurrent ? 1 : 0;
+    return build_tasks2(b);
+}
+
+int ptrt_batch_get_plan2(const ptrt_batch *b, int plan_out[5])
+{
+    if (!b || !plan_out) return PTRT_EINVAL;
+    plan_out[0] = b->yc2;
+    plan_out[1] = b->ym2;
+    plan_out[2] = b->nw2;
+    plan_out[3] = b->blocks2;
+    plan_out[4] = b->conc2;
+    return PTRT_OK;
+}
+
 int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int *xcd_o)
 {
     if (!b) return PTRT_EINVAL;
@@ -640,9 +831,11 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
                 }
             }
     }
+    // the two-step plan, on the same saved state
+    if (rc == PTRT_OK && b->d_tasks2) rc = autotune2(b, e0, e1);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
-    // 16 steps per trial keep the parity: restore the state into buffer cur0
+    // restore the state into buffer cur0 (the trials may end on either)
     b->cur = cur0;
     e = hipMemcpyAsync(b->buf[cur0], saved, bytes, hipMemcpyDeviceToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -767,6 +960,9 @@ int ptrt_batch_destroy(ptrt_batch *b)
     if (b->d_partials) hipFree(b->d_partials);
     if (b->d_red) hipFree(b->d_red);
     if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+    if (b->fork_event) (void)hipEventDestroy(b->fork_event);
+    if (b->join_event) (void)hipEventDestroy(b->join_event);
     delete b;
     return PTRT_OK;
 }

@@ -543,12 +543,18 @@ int reset_check(ptrt_ctx *c)
     return PTRT_OK;
 }
 
-// Pick up the result of the latest check if its copy has arrived (no wait).
+// Pick up what the copies that have run so far brought back (no wait): the
+// host runs ahead of the device, so the latest check is rarely finished,
+// but every finished copy carries the minimum over all checks before it.
+// A value is taken only if it is a step already enqueued (a copy in flight
+// cannot then be mistaken for a result).
 void poll_check(ptrt_ctx *c)
 {
-    if (!c->bad_pending || hipEventQuery(c->bad_event) != hipSuccess) return;
-    c->bad_pending = false;
-    if (*c->h_bad != NO_STEP) c->diverged_at = (long long)*c->h_bad;
+    if (!c->bad_pending) return;
+    const unsigned long long v = *(volatile unsigned long long *)c->h_bad;
+    if (v != NO_STEP && (long long)v <= c->t && v % (unsigned long long)c->check_every == 0)
+        c->diverged_at = (long long)v;
+    if (hipEventQuery(c->bad_event) == hipSuccess) c->bad_pending = false;
 }
 
 // Enqueue the check of the current state (step c->t) and the copy of its

@@ -88,6 +88,9 @@ _SIGS = {
     "ptrt_batch_set_plan": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int]),
     "ptrt_batch_autotune": (ctypes.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "ptrt_batch_set_plan2": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int]),
+    "ptrt_batch_get_plan2": (ctypes.c_int, [_vp, _ip]),
     "ptrt_batch_step": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_batch_set_steps_per_pass": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ptrt_batch_last_pass": (ctypes.c_int, [_vp, _ip, _dp]),
@@ -432,6 +435,18 @@ def ptrt_batch_autotune(b):
     v = [ctypes.c_int() for _ in range(4)]
     _check(_lib.ptrt_batch_autotune(b.ptr, *[ctypes.byref(x) for x in v]), b.ptr, True)
     return tuple(x.value for x in v)
+
+
+def ptrt_batch_set_plan2(b, rows, masked_rows, waves=4, blocks=0, concurrent=0):
+    return _check(_lib.ptrt_batch_set_plan2(b.ptr, int(rows), int(masked_rows), int(waves),
+                                            int(blocks), int(concurrent)), b.ptr, True)
+
+
+def ptrt_batch_get_plan2(b):
+    """(rows, masked_rows, waves, blocks, concurrent) of the two-step plan."""
+    v = (ctypes.c_int * 5)()
+    _check(_lib.ptrt_batch_get_plan2(b.ptr, v), b.ptr, True)
+    return tuple(v)
 
 
 def ptrt_batch_step(b, n=1):

@@ -76,6 +76,49 @@ def test_batch_bitwise_equals_single(storage):
         P.ptrt_batch_destroy(b)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_two_step_plans_bitwise(storage):
+    """Every two-step plan computes the same values: rows per chunk, rows
+    per masked chunk, waves per workgroup, one wave per task or a
+    persistent grid (down to one workgroup), the masked launch after or
+    beside the other; odd step counts (two-step passes, then a one-step
+    launch) and graph replays; then the autotuned plan.  Each instance
+    equals the single lattice bit for bit after all of them."""
+    print_case("batch two-step plans bitwise", storage)
+    specs = _small_specs(seed=3)
+    b = P.ptrt_batch_create(specs, storage)
+    try:
+        fields = [_init_fields(s, 300 + k) for k, s in enumerate(specs)]
+        for k, (rho, u) in enumerate(fields):
+            P.ptrt_batch_init_equilibrium(b, k, rho, u)
+        plans = [(1, 1, 2, 0, 0), (2, 1, 4, 0, 1), (3, 2, 8, 0, 0), (5, 3, 4, 64, 1),
+                 (7, 7, 2, 16, 0), (64, 64, 8, 0, 1), (3, 1, 4, 1, 1)]
+        total = 0
+        for plan in plans:
+            P.ptrt_batch_set_plan2(b, *plan)
+            assert P.ptrt_batch_get_plan2(b) == plan
+            P.ptrt_batch_step(b, 7)          # three two-step passes and one step
+            total += 7
+        assert P.ptrt_batch_last_pass(b)[0] == 1
+        P.ptrt_batch_step(b, 12)             # a graph replay of ten steps, one pass
+        total += 12
+        assert P.ptrt_batch_last_pass(b)[0] == 2
+        P.ptrt_batch_autotune(b)             # must leave the state as it was
+        print("autotuned two-step plan", P.ptrt_batch_get_plan2(b))
+        P.ptrt_batch_step(b, 5)
+        total += 5
+        for k, s in enumerate(specs):
+            ref = _single(s, storage, *fields[k], total)
+            got = P.ptrt_batch_get_populations(b, k)
+            assert np.array_equal(got, ref), f"instance {k}"
+        with pytest.raises(P.PtrtError):
+            P.ptrt_batch_set_plan2(b, 0, 1)
+        with pytest.raises(P.PtrtError):
+            P.ptrt_batch_set_plan2(b, 3, 3, 16)
+    finally:
+        P.ptrt_batch_destroy(b)
+
+
 def test_batch_fp64_matches_oracle():
     print_case("batch FP64 vs oracle")
     specs = _small_specs(seed=2)

@@ -160,14 +160,18 @@ def test_dsl_2048_stability_and_fp32_error(Re, setting):
         assert res["mass_rel_change_fp64"] < 1e-10
 
 
-def test_divergence_check_reports_the_oracle_step():
-    """The library's divergence check against the oracle's divergence step:
-    the double shear layer at 128^2, Re = 1e4, Lambda = 1/4 (Sec. 3.1 shape)
-    in FP64, checked every 10 steps.  ptrt_step returns PTRT_EDIVERGED after
-    the first check that saw a non-finite population, naming the step, and
-    ptrt_divergence_step reports that step, within two check intervals of
-    the oracle's (the two agree to 1e-12 until the growth of the unstable
-    modes amplifies their different rounding).  FP32 storage is reported."""
+def test_divergence_check_reports_the_first_non_finite_step():
+    """The library's divergence check on the double shear layer at 128^2,
+    Re = 1e4, Lambda = 1/4 (Sec. 3.1 shape), checked every 10 steps:
+    ptrt_step returns PTRT_EDIVERGED (naming the step) once a check has seen
+    a non-finite population, and the step ptrt_divergence_step reports is
+    the first checked one at which the state is not finite: a fresh run of
+    the same deterministic kernels is finite (ptrt_diagnostics) 10 steps
+    earlier and not at that step.  The oracle's divergence step for the same
+    flow is reported beside it: FP64 kernel and oracle agree to 1e-12 on
+    stable flows, but here the unstable modes amplify their different
+    rounding orders, so the two blow up within 10 % of each other, not at
+    the same step."""
     from test_oracle_stability import N, RE, U0, divergence_step, dsl_lattice
     print_case("divergence check DSL 128^2 oracle")
     ref = divergence_step(dsl_lattice(), 2560)
@@ -185,11 +189,22 @@ def test_divergence_check_reports_the_oracle_step():
                     G.step(10)
             except P.PtrtError as e:
                 err = e
-            got[storage] = G.divergence_step()
-        print(f"DSL 128^2 Lambda=1/4 {storage}: library divergence step {got[storage]} "
-              f"(oracle {ref})", flush=True)
-        assert err is not None and err.code == -5 and str(got[storage]) in str(err)
-    assert abs(got["f64"] - ref) <= 20
+            d = G.divergence_step()
+        got[storage] = d
+        print(f"DSL 128^2 Lambda=1/4 {storage}: library divergence step {d} (oracle {ref}); "
+              f"ptrt_step raised: {err}", flush=True)
+        assert err is not None and err.code == -5 and str(d) in str(err)
+        assert d > 0 and d % 10 == 0
+        with P.Lattice(0, N, N, 1, tp, 0.25, storage=storage) as G:
+            G.init_equilibrium(rho, u[:2])
+            G.step(d - 10)
+            m, k = G.diagnostics()
+            assert np.isfinite(m) and np.isfinite(k)
+            G.step(10)
+            with pytest.raises(P.PtrtError) as ei:
+                G.diagnostics()
+            assert ei.value.code == -5
+    assert abs(got["f64"] - ref) <= 0.1 * ref
 
 
 @pytest.mark.parametrize("setting", ["Lambda=1/4", "1/tau-=1.6"])
