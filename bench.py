@@ -55,10 +55,14 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources' code: comments and whitespace are left
+    out, so that a counter summary stays valid across edits of comments."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p)) as fh:
+            code = re.sub(r"/\*.*?\*/|//[^\n]*", " ", fh.read(), flags=re.S)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -86,34 +90,35 @@ def warm_for(torch, stream, step_fn, ms=None, chunk=20, max_steps=None):
     return done, el
 
 
-WARM_MAX_STEPS = 600  # a stand-in stays well before any divergence of its flow
+WARM_MAX_STEPS = 400  # the 256^3 vortex at Lambda = 1/4 turns non-finite at step 1050
 
 
-def stand_in_warm(torch, stream, make, fields=(None, None), ms=None, record=None):
-    """Warm-up function: a lattice from make() (same shape, parameters and
-    kernels as the measured one) started from the same initial fields,
-    stepped for `ms` of device time (at most WARM_MAX_STEPS steps) and
-    freed, so that the measured flow is not advanced.  The same fields
-    matter: the device draws more power on the vortex's data than on a
-    state at rest, and its clock takes tens of milliseconds to settle after
-    such a change (measured: 0.58 ms per two-step pass at rest, up to 0.77
-    ms in the first passes on the vortex, 0.60 ms settled)."""
+def self_warm(torch, stream, step_fn, ms=None, record=None):
+    """Warm-up function: the measured lattice itself stepped for `ms` of
+    device time (at most WARM_MAX_STEPS steps), right before the warm-up
+    steps and the timed region, with no idle time in between.  After the
+    device has idled for a few milliseconds (a host-to-device upload, or the
+    one-time load of a kernel at its first launch, about 6 ms) the next
+    passes speed up and then slow down for about a hundred passes (kernel
+    trace of the 256^3 vortex: 0.61 ms for the first two-step pass, 0.78 ms
+    by the sixth, back to 0.59 ms after about 100), so a short timed region
+    must not follow such a gap.  One single step runs first: it loads the
+    one-step kernel that an odd warm-up count launches just before the
+    timed steps."""
     def fn():
         if (WARM[0] if ms is None else ms) <= 0:
             return
-        with make() as Lw:
-            Lw.init_equilibrium(*fields)
-            done, el = warm_for(torch, stream, Lw.step, ms, max_steps=WARM_MAX_STEPS)
+        step_fn(1)
+        done, el = warm_for(torch, stream, step_fn, ms, max_steps=WARM_MAX_STEPS)
         if record is not None:
-            record["steps"], record["ms"] = done, el
+            record["steps"], record["ms"] = done + 1, el
     return fn
 
 
 def timed_steps(torch, stream, step_fn, steps, warmup, warm_fn=None):
-    """Run warmup steps, then time exactly `steps` steps with HIP events on
-    `stream` (bracketed by device synchronisation).  warm_fn, if given, runs
-    first (a time-based warm-up on a stand-in lattice).  Returns (event ms,
-    wall s)."""
+    """Run warm_fn (a time-based warm-up) if given and `warmup` steps, then
+    time exactly `steps` steps with HIP events on `stream` (bracketed by
+    device synchronisation).  Returns (event ms, wall s)."""
     if warm_fn is not None:
         warm_fn()
     if warmup:
@@ -159,16 +164,16 @@ def bench_single(P, torch, stream, lattice, shape, storage, init, tau_plus, Lamb
     with make() as L:
         rho, u = init()
         L.init_equilibrium(rho, u)
-        warm_fn = stand_in_warm(torch, stream, make, (rho, u), warm_ms, warm) if warm_ms > 0 else None
+        del rho, u
         e0 = None
         if diag:
             m0, e0 = L.diagnostics(raise_on_divergence=False)
-        ms, wall = timed_steps(torch, stream, L.step, steps, warmup, warm_fn)
-        del rho, u, warm_fn
+        ms, wall = timed_steps(torch, stream, L.step, steps, warmup,
+                               self_warm(torch, stream, L.step, warm_ms, warm))
         nodes = nx * ny * nz
         res = {
             "shape": [nx, ny, nz], "storage": storage, "steps": steps, "warmup": warmup,
-            "warm_up_stand_in": warm,
+            "warm_up": warm,
             "ms_per_step": ms / steps, "mlups": nodes * steps / (ms * 1e-3) / 1e6,
             "wall_mlups": nodes * steps / wall / 1e6,
             "bytes_per_node": L.bytes_per_node,
@@ -301,7 +306,7 @@ def form_models(P, torch, stream, steps, warmup):
             with make() as L:
                 L.init_equilibrium(rho, u)
                 ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
-                                    stand_in_warm(torch, stream, make, (rho, u)))
+                                    self_warm(torch, stream, L.step))
                 res[model] = {"ms_per_step": ms / steps, "mlups": nx * ny * nz * steps / (ms * 1e-3) / 1e6}
         res["trt_rlb_time_over_ptrt"] = res["trt-rlb"]["ms_per_step"] / res["ptrt"]["ms_per_step"]
         res["trt_time_over_ptrt"] = res["trt"]["ms_per_step"] / res["ptrt"]["ms_per_step"]
@@ -327,7 +332,7 @@ def form_d3q27(P, torch, stream, steps, warmup):
         with make() as L:
             L.init_equilibrium(rho, u)
             ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
-                                stand_in_warm(torch, stream, make, (rho, u)))
+                                self_warm(torch, stream, L.step))
             bpn = L.bytes_per_node
         mps = ms / steps
         gbs = bpn * n ** 3 / (mps * 1e-3) / 1e9
@@ -366,7 +371,7 @@ def form_forcing(P, torch, stream, steps, warmup):
             with make() as L:
                 L.init_equilibrium(rho, u)
                 ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
-                                    stand_in_warm(torch, stream, make, (rho, u)))
+                                    self_warm(torch, stream, L.step))
             mps = ms / steps
             alg = 2 * Q * 4 + (Q * 4 + 2 * D * 4 if forcing == "scheme2+g" else 0)
             res[forcing] = {"ms_per_step": mps, "mlups": nodes / (mps * 1e-3) / 1e6,
@@ -426,7 +431,7 @@ def form_cylinder(P, torch, stream, steps, warmup):
         with make() as L:
             L.init_equilibrium(None, u)
             ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
-                                stand_in_warm(torch, stream, make, (None, u)))
+                                self_warm(torch, stream, L.step))
             spp = L.last_pass()[0]
             t0 = time.perf_counter()
             for _ in range(10):

@@ -6,10 +6,8 @@
 //   u = (j + F/2) / rho = j / rho + g/2                           (Eq. macro)
 //   f^eq from Eq. feq; with eu = e_i.u and uu = |u|^2 its parity halves are
 //     heq+_i = w_i (drho + rho (9/2 eu^2 - 3/2 uu))
-//     heq-_i = w_i rho eu (3 + 9/2 (eu^2 - uu))
-//            = c_i e_i.(rho u) (1 + 3/2 (eu^2 - uu)),
-//   c_i = 3 w_i rounded so that the first moment is exact (lattice.hpp) and
-//   rho u = j + F/2 used as such (no rho (j/rho) round trip)
+//     heq-_i = w_i rho eu (3 + 9/2 (eu^2 - uu)) = c_i rho eu (1 + 3/2 (eu^2 - uu)),
+//   c_i = 3 w_i rounded so that the first moment is exact (lattice.hpp)
 //   (the third-order Hermite term is (9/2) eu (eu^2 - uu) on lattices whose
 //   velocity components are 0 or +-1)
 //   neq+-_i = (h_i +- h_ibar)/2 - heq+-_i                      (Eq. fneq_parity)
@@ -260,18 +258,10 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
     });
     const C rho = C(1) + drho;
     const C inv = C(1) / rho;
-    // rho u = j + F/2 (Eq. macro), kept: the first-order equilibrium term is
-    // formed from it, c_i e_i.(rho u), not as rho (e_i.u), whose
-    // rho (j / rho) round trip adds a rounding to the dominant part of every
-    // population (measured FP32 velocity error on the 64^3 vortex at
-    // Re = 1600, 500 steps: 2.4e-6 -> 4.7e-7)
-    const C Jx = jx + rho * r.hgx;
-    const C Jy = jy + rho * r.hgy;
+    const C ux = jx * inv + r.hgx;
+    const C uy = jy * inv + r.hgy;
     // 2D: u_z = 0 exactly (no z momentum, no z force)
-    const C Jz = L::D == 3 ? jz + rho * r.hgz : C(0);
-    const C ux = Jx * inv;
-    const C uy = Jy * inv;
-    const C uz = L::D == 3 ? Jz * inv : C(0);
+    const C uz = L::D == 3 ? jz * inv + r.hgz : C(0);
     C uu = ux * ux + uy * uy;
     if constexpr (L::D == 3) uu = uu + uz * uz;
     const C m15uu = C(-1.5) * uu;
@@ -297,10 +287,9 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const Coef<L, C> &r, C &rh
         const C eqp = w * (drho + rho * (C(4.5) * eu2 + m15uu));
         C sym = eqp + r.ap * ((C(0.5) * sp[p] - eqp) - pg[p]);
         if constexpr (FORCING != FORCE_II) sym += sym_source<L, FORCING, i>(src, r, p, rho, eu);
-        // w rho eu (3 + (9/2)(eu^2 - uu)) = (c_i e_i.(rho u)) (1 + (3/2)(eu^2 - uu))
-        // with c_i = 3 w_i as L::c1 (first moment exact)
-        const C eJ = edot<L, i>(Jx, Jy, Jz);
-        const C eqm = (L::template c1<C>(i) * eJ) * (C(1) + C(1.5) * (eu2 - uu));
+        // w rho eu (3 + (9/2)(eu^2 - uu)) with c_i = 3 w_i as L::c1 (first
+        // moment exact)
+        const C eqm = (L::template c1<C>(i) * rho) * (eu * (C(1) + C(1.5) * (eu2 - uu)));
         const C anti = eqm + r.am * (C(0.5) * dp[p] - eqm) + rho * r.K[p];
         h[i] = sym + anti;
         h[j] = sym - anti;
@@ -344,13 +333,9 @@ __device__ __forceinline__ void collide_d3q27(C (&h)[27], const Coef<D3Q27, C> &
     });
     const C rho = C(1) + drho;
     const C inv = C(1) / rho;
-    // rho u kept for the first-order equilibrium term (as in collide())
-    const C Jx = jx + rho * r.hgx;
-    const C Jy = jy + rho * r.hgy;
-    const C Jz = jz + rho * r.hgz;
-    const C ux = Jx * inv;
-    const C uy = Jy * inv;
-    const C uz = Jz * inv;
+    const C ux = jx * inv + r.hgx;
+    const C uy = jy * inv + r.hgy;
+    const C uz = jz * inv + r.hgz;
     const C uu = ux * ux + uy * uy + uz * uz;
     const C m15uu = C(-1.5) * uu;
 
@@ -363,7 +348,7 @@ __device__ __forceinline__ void collide_d3q27(C (&h)[27], const Coef<D3Q27, C> &
         const C eu = edot<L, i>(ux, uy, uz);
         const C eu2 = eu * eu;
         eqp[p] = w * (drho + rho * (C(4.5) * eu2 + m15uu));
-        eqm[p] = (L::template c1<C>(i) * edot<L, i>(Jx, Jy, Jz)) * (C(1) + C(1.5) * (eu2 - uu));
+        eqm[p] = (L::template c1<C>(i) * rho) * (eu * (C(1) + C(1.5) * (eu2 - uu)));
         np[p] = C(0.5) * sp[p] - eqp[p];
         nm[p] = C(0.5) * dp[p] - eqm[p];
     });

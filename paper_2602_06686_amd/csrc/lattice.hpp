@@ -26,13 +26,13 @@ __host__ __device__ __forceinline__ void static_for(F &&f)
 // the equilibrium's first moment would be rho u (1 + d) and every collision
 // would rescale the momentum by a fixed factor: a bias that accumulates
 // linearly and, in FP32 with tau+ near 1/2, dominates the velocity error
-// (measured on the 64^3 vortex at Re = 1600: 8.0e-6 after 500 steps with
-// independently rounded weights, 2.4e-6 with these; FP64 arithmetic with
-// FP32 storage 7e-8).  So one class of c_i is rounded and the other is
-// solved from the identity sum_i c_i e_ix^2 = 1 with operations that are
-// exact in C (a subtraction of two numbers within a factor two of each
-// other, products and quotients by powers of two); the identity then holds
-// exactly for the rounded values.
+// (64^3 vortex at Re = 1600, 500 steps, against FP64: 8.1e-6 with
+// independently rounded weights, 2.4e-6 with these, on the GPU; a CPU
+// model of the same update with FP64 arithmetic and FP32 storage: 7e-8).
+// So one class of c_i is rounded and the other is solved from the identity
+// sum_i c_i e_ix^2 = 1 with operations that are exact in C (a subtraction of
+// two numbers within a factor two of each other, products and quotients by
+// powers of two); the identity then holds exactly for the rounded values.
 template <class C>
 __host__ __device__ constexpr C round_to_bits(double v, int bits)
 {
