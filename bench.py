@@ -432,7 +432,7 @@ def form_cylinder(P, torch, stream, steps, warmup):
             L.init_equilibrium(None, u)
             ms, _ = timed_steps(torch, stream, L.step, steps, warmup,
                                 self_warm(torch, stream, L.step))
-            spp = L.last_pass()[0]
+            spp, pass_bytes = L.last_pass()
             t0 = time.perf_counter()
             for _ in range(10):
                 F = L.momentum_exchange()
@@ -441,7 +441,11 @@ def form_cylinder(P, torch, stream, steps, warmup):
         mps = ms / steps
         out[storage] = {"ms_per_step": mps, "mlups": n * n / (mps * 1e-3) / 1e6,
                         "steps_per_pass": spp,
-                        "achieved_gbs": bpn * n * n / (mps * 1e-3) / 1e9,
+                        # the pass's own bytes over its time; the one-step
+                        # figure is what one step per pass would have to
+                        # move at this rate (not traffic, may exceed the peak)
+                        "pass_gbs": pass_bytes / (mps * spp * 1e-3) / 1e9,
+                        "one_step_equiv_gbs": bpn * n * n / (mps * 1e-3) / 1e9,
                         "momentum_exchange_ms_host": mx,
                         "cd_after_timed_steps": 2 * F[0] / (uc * uc * D)}
     return out
@@ -476,7 +480,53 @@ def cpu_baseline(n=256, steps=12):
             "kind": "oracle",
             "sample": f"{steps} steps of the same {n}^3 D3Q19 lattice (FP64 C oracle, OpenMP over nodes), {dt:.1f} s",
             "value_one_core": n1 ** 3 * s1 / dt1 / 1e6,
-            "sample_one_core": f"{s1} steps of a {n1}^3 D3Q19 lattice on one thread, {dt1:.1f} s"}
+            "sample_one_core": f"{s1} steps of a {n1}^3 D3Q19 lattice on one thread, {dt1:.1f} s",
+            "other_workloads": cpu_baseline_2d()}
+
+
+def cpu_baseline_2d():
+    """The same oracle on bounded samples of the D2Q9 workloads (all host
+    threads): the 64^2 FP64 vortex in full (1000 steps), 10 steps of the
+    2048^2 double shear layer, and 2 steps of every lattice of the
+    512-lattice batch (walls, obstacles and forces as in the batch), one
+    lattice after the other."""
+    import lbm_inputs as I
+    from oracle import ptrt as O
+    out = {}
+    n = 64
+    rho, u = I.tgv2d(n, 0.05)
+    L = O.Lattice(O.D2Q9, n, n, 1, I.tau_plus_from_nu(0.01), 0.25)
+    L.init_equilibrium(rho, u)
+    t0 = time.perf_counter()
+    L.step(1000)
+    dt = time.perf_counter() - t0
+    out["d2q9_64_f64_tgv"] = {"value": n * n * 1000 / dt / 1e6, "unit": "MLUPS",
+                              "sample": f"1000 steps of the 64^2 vortex (in full), {dt:.2f} s"}
+    n, U0, steps = 2048, 0.05, 10
+    rho, u = I.double_shear_layer(n, U0)
+    L = O.Lattice(O.D2Q9, n, n, 1, I.tau_plus_from_nu(U0 * n / 1e4), 0.25)
+    L.init_equilibrium(rho, u[:2])
+    del rho, u
+    t0 = time.perf_counter()
+    L.step(steps)
+    dt = time.perf_counter() - t0
+    del L
+    out["d2q9_2048_dsl"] = {"value": n * n * steps / dt / 1e6, "unit": "MLUPS",
+                            "sample": f"{steps} steps of the 2048^2 double shear layer, {dt:.1f} s"}
+    steps, nodes, dt = 2, 0, 0.0
+    for sp in I.batch_specs():
+        L = O.Lattice(O.D2Q9, sp["nx"], sp["ny"], 1, sp["tau_plus"], sp["Lambda"], g=sp["g"],
+                      solid=sp["mask"])
+        L.init_equilibrium()
+        t0 = time.perf_counter()
+        L.step(steps)
+        dt += time.perf_counter() - t0
+        nodes += sp["nx"] * sp["ny"]
+        del L
+    out["batched_d2q9"] = {"value": nodes * steps / dt / 1e6, "unit": "MLUPS",
+                           "sample": f"{steps} steps of each of the 512 batch lattices ({nodes} nodes), "
+                                     f"one lattice at a time, {dt:.1f} s"}
+    return out
 
 
 def copy_calibration(torch, stream, nbytes=1 << 30):
