@@ -215,6 +215,13 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
     const int t0 = w, t1 = w + BY;
     const bool has1 = t1 <= AY;
     S raw0[L::Q], raw1[L::Q];
+    // FP64 (one workgroup per CU, so no other workgroup's work covers the
+    // load latency) keeps the loads of two planes in flight, in a second
+    // register set used on alternate planes (loop unrolled by two; measured
+    // at 256^3: 25.0 -> 29.3 GLUPS).  FP32, with two workgroups per CU,
+    // lost with the same (256^3 56.5 -> 53.4, 512^3 57.4 -> 49.8).
+    constexpr bool DEEP = sizeof(S) == 8;
+    S rawb0[DEEP ? L::Q : 1], rawb1[DEEP ? L::Q : 1];
     // row tasks in FP64 take load_row (measured at 256^3: FP64 +5.6 %;
     // FP32 +1 % at 256^3 and -1.7 % at 512^3, so FP32 keeps load_a)
     auto load_both = [&](int k) {
@@ -235,6 +242,26 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
         if (has1) finish_a(t1, it, raw1);
         finish_a(t0, it, raw0);
     };
+    // the same for the second register set (FP64 only; generic lambdas, so
+    // that they are instantiated only where called)
+    auto load_second_set = [&](auto k) {
+        if constexpr (!MASK) {
+            if (has1) {
+                if (t1 < AY)
+                    load_row(t1, k, rawb1);
+                else
+                    load_a(t1, k, rawb1);
+            }
+            load_row(t0, k, rawb0);
+        } else {
+            if (has1) load_a(t1, k, rawb1);
+            load_a(t0, k, rawb0);
+        }
+    };
+    auto finish_second_set = [&](auto it) {
+        if (has1) finish_a(t1, it, rawb1);
+        finish_a(t0, it, rawb0);
+    };
     // first-step planes zs - 1, zs and zs + 1 (ze >= zs + 1), then for
     // k = zs + 1 ... ze the second step of plane k - 1 followed by the first
     // step of plane k + 1 (past the chunk the last plane is loaded again,
@@ -248,9 +275,9 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
     finish_both(1);
     load_both(zs + 1);
     finish_both(2);
-    load_both(min(zs + 2, ze));
-    for (int k = zs + 1, it = 2;; ++k, ++it) {
-        lds_barrier();
+    // the second step of plane k - 1, iteration it (first-step planes up to
+    // k in lds)
+    auto second = [&](int k, int it) __attribute__((always_inline)) {
         {
             // B: second step at interior node (x0 + lane, y0 + w, k - 1)
             const int ax = lane + 1, ay = w + 1;
@@ -301,10 +328,35 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
                 });
             }
         }
-        lds_barrier();
-        if (k == ze) break;
-        finish_both(it + 1);
-        load_both(min(k + 2, ze));
+    };
+    load_both(min(zs + 2, ze));
+    if constexpr (DEEP) {
+        // two planes in flight: the first step of plane k + 1 takes the set
+        // loaded two iterations before, which then loads plane k + 3
+        load_second_set(min(zs + 3, ze));
+        for (int k = zs + 1, it = 2;; k += 2, it += 2) {
+            lds_barrier();
+            second(k, it);
+            lds_barrier();
+            if (k == ze) break;
+            finish_both(it + 1);
+            load_both(min(k + 3, ze));
+            lds_barrier();
+            second(k + 1, it + 1);
+            lds_barrier();
+            if (k + 1 == ze) break;
+            finish_second_set(it + 2);
+            load_second_set(min(k + 4, ze));
+        }
+    } else {
+        for (int k = zs + 1, it = 2;; ++k, ++it) {
+            lds_barrier();
+            second(k, it);
+            lds_barrier();
+            if (k == ze) break;
+            finish_both(it + 1);
+            load_both(min(k + 2, ze));
+        }
     }
 }
 
