@@ -19,7 +19,9 @@ pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2602_06686_amd.ptrt")
 
 
-def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5):
+def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5, passes=None):
+    """Populations after `steps` steps; `passes`, if a list, receives the
+    steps covered by the last kernel pass."""
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)
     rho, u = I.random_fields(rng, shape, umax=0.05)
@@ -27,6 +29,8 @@ def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5):
                    steps_per_pass=spp) as G:
         G.init_equilibrium(rho, u)
         G.step(steps)
+        if passes is not None:
+            passes.append(G.last_pass()[0])
         return G.populations()
 
 
@@ -35,14 +39,21 @@ def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5):
     (1, "f32", (3, 12, 64)), (1, "f32", (4, 10, 64)), (1, "f32", (3, 13, 128)), (1, "f32", (5, 6, 64)),
     (1, "f32", (4, 32, 64)), (1, "f32", (3, 64, 128)), (1, "f32", (2, 16, 192)),
     (1, "f64", (4, 8, 64)), (1, "f64", (3, 10, 128)),
+    # FP64 keeps two planes of loads in flight (its loop unrolled by two):
+    # chunks of 1, 2, 5 and 7 planes, and several chunks per column
+    (1, "f64", (1, 8, 64)), (1, "f64", (2, 8, 64)), (1, "f64", (5, 6, 64)), (1, "f64", (7, 16, 128)),
+    (1, "f64", (128, 128, 128)), (1, "f64", (99, 64, 64)),
     (1, "f16", (5, 16, 64)), (1, "bf16", (9, 8, 128)),
     (2, "f16", (9, 8, 64)), (2, "bf16", (4, 12, 64))])
 @pytest.mark.parametrize("steps", [1, 2, 7, 40])
 def test_two_steps_per_pass_bitwise(lat, storage, shape, steps):
     print_case("steps per pass 2 vs 1", lat, storage, shape, steps)
     a = _run(lat, shape, storage, steps, 1)
-    b = _run(lat, shape, storage, steps, 2)
+    last = []
+    b = _run(lat, shape, storage, steps, 2, passes=last)
     assert np.array_equal(a, b)
+    if lat == 1 and storage in ("f32", "f64") and steps % 2 == 0:
+        assert last == [2]          # the two-step kernel ran
 
 
 # D2Q9 (two steps per pass in FP32 and FP64): strips of 62 columns (the
