@@ -207,28 +207,17 @@ def test_divergence_check_reports_the_first_non_finite_step():
     assert abs(got["f64"] - ref) <= 0.1 * ref
 
 
-@pytest.mark.parametrize("setting", ["Lambda=1/4", "1/tau-=1.6"])
-def test_tgv3d_256_kinetic_energy_decay(setting):
-    """3D vortex at 256^3, FP32, 5000 steps (configured length): the kinetic
-    energy from the FP64 GPU reduction every 250 steps, the divergence step
-    from the library's check (every 50 steps).  The early decay follows the
-    viscous closed form exp(-6 nu k^2 t) within 2 % (kinetic-acoustic
-    exchange at Ma ~ 0.09 keeps it from being closer).  At the configured
-    Lambda = 1/4 the run diverges; the paper's optimum 1/tau- = 1.6
-    (Sec. 3.1) is run beside it and its divergence step, if any, reported."""
-    print_case("3D TGV 256^3 FP32 kinetic energy", setting)
-    n, U0 = 256, 0.05
+def _tgv3d_256_energy_series(storage, lam, n=256, U0=0.05):
+    """E(t) every 250 steps up to 5000 (FP64 GPU reduction), the final mass
+    and the divergence step from the library's check (every 50 steps)."""
     prm = I.tgv3d_params(n, U0)
-    nu, tp = prm["nu"], prm["tau_plus"]
-    lam = 0.25 if setting == "Lambda=1/4" else I.tau_minus_from_inverse(1.6, tp)
     rho, u = I.tgv3d(n, U0)
-    k = 2 * np.pi / n
-    with P.Lattice(1, n, n, n, tp, lam, storage="f32") as G:
+    with P.Lattice(1, n, n, n, prm["tau_plus"], lam, storage=storage) as G:
         G.init_equilibrium(rho, u)
         del rho, u
         G.set_divergence_check(50)
         m0, e0 = G.diagnostics()
-        series = [(0, e0)]
+        series, m = [(0, e0)], m0
         for t in range(250, 5001, 250):
             try:
                 G.step(250)
@@ -239,13 +228,42 @@ def test_tgv3d_256_kinetic_energy_decay(setting):
             if not np.isfinite(e):
                 break
             series.append((t, e))
-        diverged = G.divergence_step()
+        return series, m0, m, G.divergence_step()
+
+
+@pytest.mark.parametrize("setting", ["Lambda=1/4", "1/tau-=1.6"])
+def test_tgv3d_256_kinetic_energy_decay(setting):
+    """3D vortex at 256^3, FP32, 5000 steps (configured length): the kinetic
+    energy from the FP64 GPU reduction every 250 steps, the divergence step
+    from the library's check (every 50 steps).  The early decay follows the
+    viscous closed form exp(-6 nu k^2 t) within 2 % (kinetic-acoustic
+    exchange at Ma ~ 0.09 keeps it from being closer).  At the configured
+    Lambda = 1/4 the run diverges; at the paper's optimum 1/tau- = 1.6
+    (Sec. 3.1) it stays finite, and its whole energy history, into the
+    nonlinear stage, equals that of the same run in FP64 storage (whose
+    update matches the oracle to 1e-12 elsewhere) to 1e-4."""
+    print_case("3D TGV 256^3 FP32 kinetic energy", setting)
+    n, U0 = 256, 0.05
+    prm = I.tgv3d_params(n, U0)
+    nu, tp = prm["nu"], prm["tau_plus"]
+    lam = 0.25 if setting == "Lambda=1/4" else I.tau_minus_from_inverse(1.6, tp)
+    k = 2 * np.pi / n
+    series, m0, m, diverged = _tgv3d_256_energy_series("f32", lam)
+    e0 = series[0][1]
     print(f"3D TGV 256^3 {setting} E(t)/E0:", [(t, round(e / e0, 5)) for t, e in series],
           f"diverged at step {diverged}" if diverged >= 0 else "finite through 5000 steps",
           flush=True)
     t1, e1 = series[2]
     assert abs(e1 / e0 - np.exp(-6 * nu * k * k * t1)) < 2e-2
-    if diverged < 0:
-        assert abs(m - m0) < 1e-5 * m0
     if setting == "Lambda=1/4":
         assert 0 < diverged <= 5000
+        return
+    assert diverged < 0 and len(series) == 21
+    assert abs(m - m0) < 1e-5 * m0
+    ref, _, _, d64 = _tgv3d_256_energy_series("f64", lam)
+    assert d64 < 0 and len(ref) == 21
+    dev = max(abs(e / er - 1) for (_, e), (_, er) in zip(series, ref))
+    print(f"3D TGV 256^3 1/tau-=1.6: E(t) in FP32 vs FP64 storage, largest relative "
+          f"difference over 5000 steps {dev:.2e}; E(5000)/E0 = {ref[-1][1] / ref[0][1]:.5f}",
+          flush=True)
+    assert dev < 1e-4
