@@ -481,49 +481,50 @@ def cpu_baseline(n=256, steps=12):
             "sample": f"{steps} steps of the same {n}^3 D3Q19 lattice (FP64 C oracle, OpenMP over nodes), {dt:.1f} s",
             "value_one_core": n1 ** 3 * s1 / dt1 / 1e6,
             "sample_one_core": f"{s1} steps of a {n1}^3 D3Q19 lattice on one thread, {dt1:.1f} s",
-            "other_workloads": cpu_baseline_2d()}
+            "other_workloads": cpu_baseline_2d(cores)}
 
 
-def cpu_baseline_2d():
+def cpu_baseline_2d(cores):
     """The same oracle on bounded samples of the D2Q9 workloads (all host
     threads): the 64^2 FP64 vortex in full (1000 steps), 10 steps of the
     2048^2 double shear layer, and 2 steps of every lattice of the
     512-lattice batch (walls, obstacles and forces as in the batch), one
-    lattice after the other."""
+    lattice after the other.  The thread count is passed explicitly: the
+    one-thread run before leaves OpenMP's default at one thread."""
     import lbm_inputs as I
     from oracle import ptrt as O
     out = {}
     n = 64
     rho, u = I.tgv2d(n, 0.05)
-    L = O.Lattice(O.D2Q9, n, n, 1, I.tau_plus_from_nu(0.01), 0.25)
+    L = O.Lattice(O.D2Q9, n, n, 1, I.tau_plus_from_nu(0.01), 0.25, nthreads=cores)
     L.init_equilibrium(rho, u)
     t0 = time.perf_counter()
     L.step(1000)
     dt = time.perf_counter() - t0
-    out["d2q9_64_f64_tgv"] = {"value": n * n * 1000 / dt / 1e6, "unit": "MLUPS",
+    out["d2q9_64_f64_tgv"] = {"value": n * n * 1000 / dt / 1e6, "unit": "MLUPS", "cores": cores,
                               "sample": f"1000 steps of the 64^2 vortex (in full), {dt:.2f} s"}
     n, U0, steps = 2048, 0.05, 10
     rho, u = I.double_shear_layer(n, U0)
-    L = O.Lattice(O.D2Q9, n, n, 1, I.tau_plus_from_nu(U0 * n / 1e4), 0.25)
+    L = O.Lattice(O.D2Q9, n, n, 1, I.tau_plus_from_nu(U0 * n / 1e4), 0.25, nthreads=cores)
     L.init_equilibrium(rho, u[:2])
     del rho, u
     t0 = time.perf_counter()
     L.step(steps)
     dt = time.perf_counter() - t0
     del L
-    out["d2q9_2048_dsl"] = {"value": n * n * steps / dt / 1e6, "unit": "MLUPS",
+    out["d2q9_2048_dsl"] = {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
                             "sample": f"{steps} steps of the 2048^2 double shear layer, {dt:.1f} s"}
     steps, nodes, dt = 2, 0, 0.0
     for sp in I.batch_specs():
         L = O.Lattice(O.D2Q9, sp["nx"], sp["ny"], 1, sp["tau_plus"], sp["Lambda"], g=sp["g"],
-                      solid=sp["mask"])
+                      solid=sp["mask"], nthreads=cores)
         L.init_equilibrium()
         t0 = time.perf_counter()
         L.step(steps)
         dt += time.perf_counter() - t0
         nodes += sp["nx"] * sp["ny"]
         del L
-    out["batched_d2q9"] = {"value": nodes * steps / dt / 1e6, "unit": "MLUPS",
+    out["batched_d2q9"] = {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
                            "sample": f"{steps} steps of each of the 512 batch lattices ({nodes} nodes), "
                                      f"one lattice at a time, {dt:.1f} s"}
     return out
