@@ -169,7 +169,8 @@ int ptrt_set_forcing(ptrt_ctx *ctx, int forcing);
 /* Steps per pass over the populations (1 or 2; default 2).  With 2, pairs
  * of steps run as one kernel that keeps the first step's results in LDS
  * (temporal blocking) where the configuration allows it and it measured
- * faster: PTRT_MODEL_PTRT and PTRT_FORCING_SCHEME2, and either D3Q19 in
+ * faster: PTRT_FORCING_SCHEME2 with PTRT_MODEL_PTRT (or, without solid
+ * nodes or open x, PTRT_MODEL_TRT_RLB or PTRT_MODEL_TRT), and either D3Q19 in
  * FP32 or FP64 with nx a multiple of 64 and ny >= 4 (with solid nodes:
  * from 2^24 nodes on, while at most 5 % of the kernel's column chunks have
  * a solid within one row), or D2Q9 in FP32 or FP64 (with solid nodes or

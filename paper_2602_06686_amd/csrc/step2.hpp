@@ -95,12 +95,18 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// P-TRT collision of the lattice (the hybrid of Eq. PTRT_D3Q27 on D3Q27).
-template <class L, class C>
-__device__ __forceinline__ void collide_ptrt(C (&h)[L::Q], const Coef<L, C> &r, C &rho, C &ux,
+// Collision of a pass: P-TRT (the hybrid of Eq. PTRT_D3Q27 on D3Q27), or
+// for the efficiency comparison TRT-RLB (Eq. TRT-RLB) or standard TRT, the
+// same functions as in the one-step kernel (default forcing).
+template <class L, class C, int MODEL = MODEL_PTRT>
+__device__ __forceinline__ void collide_pass(C (&h)[L::Q], const Coef<L, C> &r, C &rho, C &ux,
                                              C &uy, C &uz)
 {
-    if constexpr (L::Q == 27)
+    if constexpr (MODEL == MODEL_TRT_RLB)
+        collide_trt_rlb<L, C>(h, r, rho, ux, uy, uz);
+    else if constexpr (MODEL == MODEL_TRT)
+        collide<L, C, false>(h, r, rho, ux, uy, uz);
+    else if constexpr (L::Q == 27)
         collide_d3q27<C, false>(h, r, rho, ux, uy, uz);
     else
         collide<L, C, true>(h, r, rho, ux, uy, uz);
@@ -112,7 +118,7 @@ __device__ __forceinline__ void collide_ptrt(C (&h)[L::Q], const Coef<L, C> &r, 
 // steps (the first step pulls through pull<L, S, true>; the second takes
 // the node's own first-step value of the opposite direction where the
 // source node is solid, and solid nodes are not stored).
-template <class L, class S, bool NT, bool MASK>
+template <class L, class S, bool NT, bool MASK, int MODEL = MODEL_PTRT>
 __device__ __forceinline__ void
 step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
               const Geom &g, const Coef<L, typename Codec<S>::compute> &r, S *lds, int x0, int y0,
@@ -198,7 +204,7 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
             h[i] = Codec<S>::load(&raw[i]);
         });
         C rho, ux, uy, uz;
-        collide_ptrt<L, C>(h, r, rho, ux, uy, uz);
+        collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
         if (!valid) return;
         const int a = ay * AX + ax;
         static_for<L::Q>([&](auto ic) {
@@ -320,7 +326,7 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
                 });
             }
             C rho, ux, uy, uz;
-            collide_ptrt<L, C>(h, r, rho, ux, uy, uz);
+            collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
             if (store) {
                 static_for<L::Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
@@ -361,7 +367,7 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
 }
 
 // Grid (x blocks, y blocks, z chunks of zc planes), without solids.
-template <class L, class S, bool NT>
+template <class L, class S, bool NT, int MODEL = MODEL_PTRT>
 __global__ void __launch_bounds__((64 * Step2Shape<L, S>::WAVES))
 k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         Coef<L, typename Codec<S>::compute> r, int zc)
@@ -371,8 +377,8 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     int bx, by, bz;
     xcd_block(bx, by, bz);
     const int zs = bz * zc;
-    step2_3d_task<L, S, NT, false>(src, dst, nullptr, g, r, lds, bx * SH::BX, by * SH::BY, zs,
-                                   min(zs + zc, g.nz));
+    step2_3d_task<L, S, NT, false, MODEL>(src, dst, nullptr, g, r, lds, bx * SH::BX,
+                                          by * SH::BY, zs, min(zs + zc, g.nz));
 }
 
 // Task list (with solids): workgroup t runs tasks[t] = {x0, y0, zs, ze}.
@@ -437,7 +443,7 @@ __device__ __forceinline__ void wave_lds_sync()
 // first-step values, like bounce-back), and the outlet node's entering
 // ones come from zou_he_east; the first-step values across the x seam are
 // then never read.
-template <class S, bool NT, bool MASK, bool OPEN = false>
+template <class S, bool NT, bool MASK, bool OPEN = false, int MODEL = MODEL_PTRT>
 __device__ __forceinline__ void
 step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
               const Geom &g, const Coef<D2Q9, typename Codec<S>::compute> &r, S *lds, int x0,
@@ -532,7 +538,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
         });
         if constexpr (OPEN) open_fix(h, ax);
         C rho, ux, uy, uz;
-        collide<L, C, true>(h, r, rho, ux, uy, uz);
+        collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
         static_for<L::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int c = K::cls(i);
@@ -577,7 +583,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
             });
             if constexpr (OPEN) open_fix(h, bxg);
             C rho, ux, uy, uz;
-            collide<L, C, true>(h, r, rho, ux, uy, uz);
+            collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
             char *db = reinterpret_cast<char *>(dst) + o[1];
             static_for<L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -619,7 +625,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
 // the last partial.  The NW waves of a workgroup run independent tasks
 // (neighbouring strips of one chunk).  Eight waves per SIMD: FP32 fits in
 // 64 VGPRs (measured +1.5 % at 4096^2).
-template <class S, bool NT, int NW, bool MASK, bool OPEN>
+template <class S, bool NT, int NW, bool MASK, bool OPEN, int MODEL = MODEL_PTRT>
 __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
@@ -645,8 +651,8 @@ k_step2_2d(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__rest
         ys = by * yc;
         ye = min(ys + yc, g.ny);
     }
-    step2_2d_task<S, NT, MASK, OPEN>(src, dst, mask, g, r, lds_all + w * (SH::K::planes * SH::W),
-                                     x0, ys, ye);
+    step2_2d_task<S, NT, MASK, OPEN, MODEL>(src, dst, mask, g, r,
+                                            lds_all + w * (SH::K::planes * SH::W), x0, ys, ye);
 }
 
 } // namespace ptrt

@@ -174,7 +174,12 @@ bool step2_3d_task_lists(const Geom &g, const uint8_t *near, std::vector<int4> &
 template <class L>
 bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
 {
-    if ((a.open && L::D != 2) || !a.row || a.model != MODEL_PTRT || a.forcing != FORCE_II)
+    if ((a.open && L::D != 2) || !a.row || a.forcing != FORCE_II) return false;
+    // the comparison models (TRT-RLB, TRT) run the same passes without
+    // solids or open boundaries, for the efficiency comparison where the
+    // pass is bound by instruction issue
+    if (a.model != MODEL_PTRT &&
+        (a.model == MODEL_PTRT_EXACT || a.has_mask || a.open))
         return false;
     if constexpr (L::D == 2) {
         // measured against one step per pass: a gain at every size in FP32
@@ -212,31 +217,37 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                     *pass_bytes = (2.0 * L::Q * sizeof(S) + (a.has_mask ? 1.0 : 0.0)) *
                                   a.g.nx * a.g.ny;
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
-                auto go = [&](auto mc, auto oc, const int4 *list, int n) {
+                auto go = [&](auto mc, auto oc, const int4 *list, int n, auto modc) {
                     constexpr bool M = decltype(mc)::value, O = decltype(oc)::value;
+                    constexpr int MD = decltype(modc)::value;
                     if (n == 0) return;
                     const dim3 grid((n + NW - 1) / NW, 1, 1);
                     if (a.nt)
-                        hipLaunchKernelGGL((k_step2_2d<S, true, NW, M, O>), grid, dim3(SH::W * NW),
-                                           0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
-                                           list, a.g, r, yc, strips, n);
+                        hipLaunchKernelGGL((k_step2_2d<S, true, NW, M, O, MD>), grid,
+                                           dim3(SH::W * NW), 0, a.stream, (const S *)a.src,
+                                           (S *)a.dst, a.mask, list, a.g, r, yc, strips, n);
                     else
-                        hipLaunchKernelGGL((k_step2_2d<S, false, NW, M, O>), grid, dim3(SH::W * NW),
-                                           0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
-                                           list, a.g, r, yc, strips, n);
+                        hipLaunchKernelGGL((k_step2_2d<S, false, NW, M, O, MD>), grid,
+                                           dim3(SH::W * NW), 0, a.stream, (const S *)a.src,
+                                           (S *)a.dst, a.mask, list, a.g, r, yc, strips, n);
                 };
                 using F = std::false_type;
                 using T = std::true_type;
+                using PT = std::integral_constant<int, MODEL_PTRT>;
                 if (a.has_mask || a.open) {
-                    go(F{}, F{}, a.tasks_plain, a.n_plain);
+                    go(F{}, F{}, a.tasks_plain, a.n_plain, PT{});
                     if (a.has_mask && a.open)
-                        go(T{}, T{}, a.tasks_special, a.n_special);
+                        go(T{}, T{}, a.tasks_special, a.n_special, PT{});
                     else if (a.has_mask)
-                        go(T{}, F{}, a.tasks_special, a.n_special);
+                        go(T{}, F{}, a.tasks_special, a.n_special, PT{});
                     else
-                        go(F{}, T{}, a.tasks_special, a.n_special);
+                        go(F{}, T{}, a.tasks_special, a.n_special, PT{});
+                } else if (a.model == MODEL_TRT_RLB) {
+                    go(F{}, F{}, nullptr, tasks, std::integral_constant<int, MODEL_TRT_RLB>{});
+                } else if (a.model == MODEL_TRT) {
+                    go(F{}, F{}, nullptr, tasks, std::integral_constant<int, MODEL_TRT>{});
                 } else {
-                    go(F{}, F{}, nullptr, tasks);
+                    go(F{}, F{}, nullptr, tasks, PT{});
                 }
             }
             return PTRT_OK;
@@ -278,12 +289,22 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                     };
                     go(std::false_type{}, a.tasks_plain, a.n_plain);
                     go(std::true_type{}, a.tasks_special, a.n_special);
-                } else if (a.nt) {
-                    hipLaunchKernelGGL((k_step2<L, S, true>), grid, block, 0, a.stream,
-                                       (const S *)a.src, (S *)a.dst, a.g, r, zc);
                 } else {
-                    hipLaunchKernelGGL((k_step2<L, S, false>), grid, block, 0, a.stream,
-                                       (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                    auto grid_pass = [&](auto modc) {
+                        constexpr int MD = decltype(modc)::value;
+                        if (a.nt)
+                            hipLaunchKernelGGL((k_step2<L, S, true, MD>), grid, block, 0,
+                                               a.stream, (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                        else
+                            hipLaunchKernelGGL((k_step2<L, S, false, MD>), grid, block, 0,
+                                               a.stream, (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                    };
+                    if (a.model == MODEL_TRT_RLB)
+                        grid_pass(std::integral_constant<int, MODEL_TRT_RLB>{});
+                    else if (a.model == MODEL_TRT)
+                        grid_pass(std::integral_constant<int, MODEL_TRT>{});
+                    else
+                        grid_pass(std::integral_constant<int, MODEL_PTRT>{});
                 }
                 launched = true;
             }

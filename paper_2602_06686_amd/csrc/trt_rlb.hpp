@@ -60,56 +60,81 @@ __device__ __forceinline__ void collide_trt_rlb(C (&h)[L::Q], const Coef<L, C> &
         fneq[i] = h[i] - heq[i];
     });
 
-    // Hermite moments of the non-equilibrium part (Eq. projection)
+    // Hermite moments of the non-equilibrium part (Eq. projection).  Terms
+    // whose Hermite coefficient vanishes for a direction are left out at
+    // compile time (IEEE arithmetic does not drop a product by zero), so the
+    // model pays only for its nonzero terms, as in the paper's cost count.
     C Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
     C Bxxy = 0, Bxyy = 0, Bxxz = 0, Byyz = 0, Bxzz = 0, Byzz = 0, Bxyz = 0;
     C Jx = 0, Jy = 0, Jz = 0;
+#define PTRT_ACC(acc, coef)                                                                       \
+    if constexpr ((coef) != 0.0) acc += C(coef) * f
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using H = Herm<L, i>;
         const C f = fneq[i];
-        Axx += C(H::xx) * f;
-        Ayy += C(H::yy) * f;
-        Axy += C(H::xy) * f;
-        Bxxy += C(H::xxy) * f;
-        Bxyy += C(H::xyy) * f;
-        Jx += C(H::ex) * f;
-        Jy += C(H::ey) * f;
+        PTRT_ACC(Axx, H::xx);
+        PTRT_ACC(Ayy, H::yy);
+        PTRT_ACC(Axy, H::xy);
+        PTRT_ACC(Bxxy, H::xxy);
+        PTRT_ACC(Bxyy, H::xyy);
+        PTRT_ACC(Jx, H::ex);
+        PTRT_ACC(Jy, H::ey);
         if constexpr (L::D == 3) {
-            Azz += C(H::zz) * f;
-            Axz += C(H::xz) * f;
-            Ayz += C(H::yz) * f;
-            Bxxz += C(H::xxz) * f;
-            Byyz += C(H::yyz) * f;
-            Bxzz += C(H::xzz) * f;
-            Byzz += C(H::yzz) * f;
-            Jz += C(H::ez) * f;
-            if constexpr (L::Q == 27) Bxyz += C(H::xyz) * f;
+            PTRT_ACC(Azz, H::zz);
+            PTRT_ACC(Axz, H::xz);
+            PTRT_ACC(Ayz, H::yz);
+            PTRT_ACC(Bxxz, H::xxz);
+            PTRT_ACC(Byyz, H::yyz);
+            PTRT_ACC(Bxzz, H::xzz);
+            PTRT_ACC(Byzz, H::yzz);
+            PTRT_ACC(Jz, H::ez);
+            if constexpr (L::Q == 27) PTRT_ACC(Bxyz, H::xyz);
         }
     });
 
-    // reconstruction (Eq. R2R3_hermite) and update (Eq. TRT-RLB)
+    // reconstruction (Eq. R2R3_hermite) and update (Eq. TRT-RLB); the
+    // diagonal second-order coefficients never vanish (2/3 or -1/3)
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         using H = Herm<L, i>;
         const C w = C(L::w(i));
-        C r2 = C(H::xx) * Axx + C(H::yy) * Ayy + C(2.0 * H::xy) * Axy;
-        C r3, p1 = C(H::ex) * Jx + C(H::ey) * Jy;
-        if constexpr (L::Q == 27) {
-            r2 += C(H::zz) * Azz + C(2.0 * H::xz) * Axz + C(2.0 * H::yz) * Ayz;
-            p1 += C(H::ez) * Jz;
-            r3 = C(13.5) * (C(H::xxy) * Bxxy + C(H::xyy) * Bxyy + C(H::xxz) * Bxxz +
-                            C(H::yyz) * Byyz + C(H::xzz) * Bxzz + C(H::yzz) * Byzz) +
-                 C(27.0 * H::xyz) * Bxyz;
-        } else if constexpr (L::D == 3) {
-            r2 += C(H::zz) * Azz + C(2.0 * H::xz) * Axz + C(2.0 * H::yz) * Ayz;
-            p1 += C(H::ez) * Jz;
-            // Gram-inverse projection per overlapping pair (xxy, yzz), (xxz, yyz), (xyy, xzz)
-            r3 = C(9) * (C(H::xxy) * (C(2) * Bxxy + Byzz) + C(H::yzz) * (Bxxy + C(2) * Byzz) +
-                         C(H::xxz) * (C(2) * Bxxz + Byyz) + C(H::yyz) * (Bxxz + C(2) * Byyz) +
-                         C(H::xyy) * (C(2) * Bxyy + Bxzz) + C(H::xzz) * (Bxyy + C(2) * Bxzz));
-        } else {
-            r3 = C(13.5) * (C(H::xxy) * Bxxy + C(H::xyy) * Bxyy);
+        C r2 = C(H::xx) * Axx + C(H::yy) * Ayy;
+        if constexpr (L::D == 3) r2 += C(H::zz) * Azz;
+        C p1 = C(0), r3 = C(0);
+        {
+#define PTRT_TERM(acc, coef, val)                                                                 \
+    if constexpr ((coef) != 0.0) acc += C(coef) * (val)
+            PTRT_TERM(r2, 2.0 * H::xy, Axy);
+            PTRT_TERM(p1, H::ex, Jx);
+            PTRT_TERM(p1, H::ey, Jy);
+            if constexpr (L::D == 3) {
+                PTRT_TERM(r2, 2.0 * H::xz, Axz);
+                PTRT_TERM(r2, 2.0 * H::yz, Ayz);
+                PTRT_TERM(p1, H::ez, Jz);
+            }
+            if constexpr (L::Q == 27) {
+                PTRT_TERM(r3, 13.5 * H::xxy, Bxxy);
+                PTRT_TERM(r3, 13.5 * H::xyy, Bxyy);
+                PTRT_TERM(r3, 13.5 * H::xxz, Bxxz);
+                PTRT_TERM(r3, 13.5 * H::yyz, Byyz);
+                PTRT_TERM(r3, 13.5 * H::xzz, Bxzz);
+                PTRT_TERM(r3, 13.5 * H::yzz, Byzz);
+                PTRT_TERM(r3, 27.0 * H::xyz, Bxyz);
+            } else if constexpr (L::D == 3) {
+                // Gram-inverse projection per overlapping pair (xxy, yzz),
+                // (xxz, yyz), (xyy, xzz)
+                PTRT_TERM(r3, 9.0 * H::xxy, C(2) * Bxxy + Byzz);
+                PTRT_TERM(r3, 9.0 * H::yzz, Bxxy + C(2) * Byzz);
+                PTRT_TERM(r3, 9.0 * H::xxz, C(2) * Bxxz + Byyz);
+                PTRT_TERM(r3, 9.0 * H::yyz, Bxxz + C(2) * Byyz);
+                PTRT_TERM(r3, 9.0 * H::xyy, C(2) * Bxyy + Bxzz);
+                PTRT_TERM(r3, 9.0 * H::xzz, Bxyy + C(2) * Bxzz);
+            } else {
+                PTRT_TERM(r3, 13.5 * H::xxy, Bxxy);
+                PTRT_TERM(r3, 13.5 * H::xyy, Bxyy);
+            }
+#undef PTRT_TERM
         }
         const C R2 = w * C(4.5) * r2;
         const C P1 = w * C(3) * p1;
@@ -123,6 +148,7 @@ __device__ __forceinline__ void collide_trt_rlb(C (&h)[L::Q], const Coef<L, C> &
         });
         h[i] = heq[i] + r.ap * (R2 + P1) + r.am * R3 + src;
     });
+#undef PTRT_ACC
     rho_o = rho;
     ux_o = ux;
     uy_o = uy;
