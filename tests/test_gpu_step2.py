@@ -357,3 +357,30 @@ def test_two_steps_per_pass_d3q19_solids_used_where_it_pays():
     cube = np.zeros((128, 512, 256), dtype=np.uint8)
     cube[48:80, 240:272, 112:144] = 1
     assert _last_pass_3d(cube, "f32")[0] == 1
+
+
+def _random_shapes(seed, n):
+    """Seeded lattice shapes for the two-step pass: D3Q19 with nx a multiple
+    of 64 (the pass's requirement) and any ny >= 4, nz >= 1; D2Q9 of any
+    size from one row up, so that strips, row chunks and z chunks end
+    ragged in every way."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        if k % 2 == 0:
+            out.append((1, (int(rng.integers(1, 40)), int(rng.integers(4, 41)),
+                            64 * int(rng.integers(1, 5)))))
+        else:
+            out.append((0, (1, int(rng.integers(1, 300)), int(rng.integers(2, 300)))))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("lat,shape", _random_shapes(2602, 16))
+def test_two_steps_per_pass_random_shapes_bitwise(storage, lat, shape):
+    """Seeded random shapes, 9 steps (four two-step passes and one single
+    step): bit-identical to one step per pass."""
+    print_case("steps per pass 2 vs 1, random shape", lat, storage, shape)
+    a = _run(lat, shape, storage, 9, 1, seed=11)
+    b = _run(lat, shape, storage, 9, 2, seed=11)
+    assert np.array_equal(a, b)
