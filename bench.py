@@ -9,7 +9,8 @@ form (512 uneven lattices, graph-replayed two-step passes, one step per
 pass with the autotuned tile plan, and the one-launch-per-lattice
 comparison), and the two D2Q9 single-lattice
 configurations (2048^2 double shear layer FP32, 64^2 Taylor-Green FP64),
-the collision-model comparison, D3Q27 (hybrid P-TRT, FP32 / FP16, and
+the collision-model comparison (P-TRT, TRT-RLB, TRT with one and with two
+steps per pass), D3Q27 (hybrid P-TRT, FP32 / FP16, and
 its comparison models) on the 256^3 vortex, the forcing schemes (Scheme II
 with the cubic correction, Scheme I) against the default, a 4096^2 FP64
 channel with walls (one and two steps per pass), and the square cylinder
