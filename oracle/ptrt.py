@@ -204,7 +204,9 @@ class Lattice:
     """A whole lattice advanced by the oracle.
 
     ``f`` holds the pre-collision populations at the current time, in the
-    oracle's node-major layout ``[N][Q]``.
+    oracle's node-major layout ``[N][Q]``.  ``nthreads`` > 0 sets the
+    OpenMP thread count for this and every later call in the process
+    (OpenMP's setting is global); 0 keeps the current setting.
     """
 
     def __init__(self, lat, nx, ny, nz, tau_plus, Lambda, g=None, solid=None,
