@@ -12,7 +12,9 @@
   1/tau- = 1.6.  No printed numbers pin this flow ("parity unpinned" beyond
   the FP64 step check).
 * 3D Taylor-Green vortex at 256^3, FP32: kinetic energy from the FP64 GPU
-  reduction; the early decay follows exp(-6 nu k^2 t) to within 2 %.
+  reduction; the early decay follows exp(-6 nu k^2 t) to within 2 %, and at
+  1/tau- = 1.6 the whole 5000-step energy history equals that of the
+  FP64-storage run to 1e-4.
 """
 import numpy as np
 import pytest
