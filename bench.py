@@ -4,7 +4,8 @@ Headline (``value``): MLUPS of the fused D3Q19 FP32 step on the 256^3
 triply periodic Taylor-Green vortex (U0 = 0.05, Re = 1600, Lambda = 1/4),
 inputs resident in HBM, timed with HIP events on the stream the kernels run
 on.  The same JSON line carries the other forms of the metric:
-D3Q19 512^3 with FP32 vs FP16 vs BF16 shifted storage, the batched D2Q9
+D3Q19 512^3 with FP32 vs FP16 vs BF16 shifted storage (round to nearest and
+stochastic rounding), the batched D2Q9
 form (512 uneven lattices, graph-replayed two-step passes, one step per
 pass with the autotuned tile plan, and the one-launch-per-lattice
 comparison), and the two D2Q9 single-lattice
@@ -614,7 +615,9 @@ def main():
         # (two steps per pass is built for FP32 only); the FP32 two-step
         # pass is reported beside it
         for st, spp, key in (("f32", 1, "d3q19_512_f32"), ("f16", 2, "d3q19_512_f16"),
-                             ("bf16", 2, "d3q19_512_bf16"), ("f32", 2, "d3q19_512_f32_two_steps")):
+                             ("bf16", 2, "d3q19_512_bf16"), ("f16sr", 2, "d3q19_512_f16sr"),
+                             ("bf16sr", 2, "d3q19_512_bf16sr"),
+                             ("f32", 2, "d3q19_512_f32_two_steps")):
             log(f"D3Q19 {st} 512^3 (steps per pass {spp})")
             forms[key] = form_d3q19(P, torch, stream, 512, st, max(20, K // 2), max(2, W // 2),
                                     inv_tau_minus=1.6, steps_per_pass=spp)
@@ -622,6 +625,7 @@ def main():
         f32 = forms["d3q19_512_f32"]["mlups"]
         forms["fp16_over_fp32_512"] = forms["d3q19_512_f16"]["mlups"] / f32
         forms["bf16_over_fp32_512"] = forms["d3q19_512_bf16"]["mlups"] / f32
+        forms["fp16sr_over_fp32_512"] = forms["d3q19_512_f16sr"]["mlups"] / f32
         best = forms["d3q19_512_f32_two_steps"]["mlups"]
         forms["fp16_over_fp32_two_steps_512"] = forms["d3q19_512_f16"]["mlups"] / best
     if only in (None, "batch"):

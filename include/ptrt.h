@@ -78,7 +78,23 @@ typedef struct ptrt_batch ptrt_batch;
 
 enum ptrt_lattice { PTRT_D2Q9 = 0, PTRT_D3Q19 = 1, PTRT_D3Q27 = 2 };
 
-enum ptrt_storage { PTRT_F64 = 0, PTRT_F32 = 1, PTRT_F16 = 2, PTRT_BF16 = 3 };
+/* Storage of the populations as shifted values h_i = f_i - w_i (the
+ * collision arithmetic is FP32 for the 16-bit types, FP64 for PTRT_F64).
+ * PTRT_F16 / PTRT_BF16 round each store to nearest even.  PTRT_F16_SR /
+ * PTRT_BF16_SR keep the same 16-bit formats but round each store of a step
+ * stochastically (up with the probability given by the value's position
+ * between its two neighbours; the dither is a hash of the value, so runs
+ * are reproducible), which keeps small per-step changes from being lost
+ * systematically on fine lattices; the initial state and
+ * ptrt_set_populations still round to nearest. */
+enum ptrt_storage {
+    PTRT_F64 = 0,
+    PTRT_F32 = 1,
+    PTRT_F16 = 2,
+    PTRT_BF16 = 3,
+    PTRT_F16_SR = 4,
+    PTRT_BF16_SR = 5
+};
 
 /* Collision model of ptrt_step: P-TRT (the method, Eq. PTRT) or, for
  * comparison, TRT-RLB (Eq. TRT-RLB: Hermite projection of the

@@ -1,5 +1,8 @@
 // Storage types of the shifted populations h_i = f_i - w_i and their
-// conversion to the compute type.  FP16 and BF16 round to nearest even.
+// conversion to the compute type.  FP16 and BF16 round to nearest even;
+// their stochastic-rounding variants (f16sr_t, bf16sr_t: the same bits in
+// memory) round each store up or down with the probability given by its
+// distance to the two neighbours.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,6 +51,7 @@ struct Codec<_Float16> {
         const _Float16 hv = (_Float16)v;
         if constexpr (NT) __builtin_nontemporal_store(hv, p); else *p = hv;
     }
+    __device__ __forceinline__ static void store_nearest(_Float16 *p, float v) { *p = (_Float16)v; }
 };
 
 template <>
@@ -63,6 +67,62 @@ struct Codec<bf16_t> {
         const bf16_t b = (bf16_t)v;
         if constexpr (NT) __builtin_nontemporal_store(b, p); else *p = b;
     }
+    __device__ __forceinline__ static void store_nearest(bf16_t *p, float v) { *p = (bf16_t)v; }
+};
+
+// Stochastic rounding: v plus a uniform dither of one unit in the last
+// place of the target format (ulp_scale: 2^-mantissa bits; min_ulp: the
+// unit of its smallest exponent), then the conversion's round to nearest,
+// so that v rounds up with probability equal to its distance from the
+// lower neighbour in units of the gap.  The dither is a hash of v's bits
+// (deterministic: the same value always rounds the same way; a value that
+// changes in its low bits from one step to the next draws a new dither).
+__device__ __forceinline__ float sr_dither(float v, float ulp_scale, float min_ulp)
+{
+    const unsigned b = __float_as_uint(v);
+    unsigned h = b * 0x9E3779B1u;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    const float r = (float)(h >> 8) * (1.0f / 16777216.0f) - 0.5f;
+    const float e2 = __uint_as_float(b & 0x7F800000u);
+    const float ulp = fmaxf(e2 * ulp_scale, min_ulp);
+    return fmaf(r, ulp, v);
+}
+
+struct f16sr_t {
+    _Float16 v;
+};
+struct bf16sr_t {
+    bf16_t v;
+};
+
+template <>
+struct Codec<f16sr_t> {
+    using compute = float;
+    static constexpr int bytes = 2;
+    __device__ __forceinline__ static float load(const f16sr_t *p) { return (float)p->v; }
+    template <bool NT = false>
+    __device__ __forceinline__ static void store(f16sr_t *p, float v)
+    {
+        const _Float16 hv = (_Float16)sr_dither(v, 0x1p-10f, 0x1p-24f);
+        if constexpr (NT) __builtin_nontemporal_store(hv, &p->v); else p->v = hv;
+    }
+    __device__ __forceinline__ static void store_nearest(f16sr_t *p, float v) { p->v = (_Float16)v; }
+};
+
+template <>
+struct Codec<bf16sr_t> {
+    using compute = float;
+    static constexpr int bytes = 2;
+    __device__ __forceinline__ static float load(const bf16sr_t *p) { return (float)p->v; }
+    template <bool NT = false>
+    __device__ __forceinline__ static void store(bf16sr_t *p, float v)
+    {
+        const bf16_t b = (bf16_t)sr_dither(v, 0x1p-7f, 0x1p-133f);
+        if constexpr (NT) __builtin_nontemporal_store(b, &p->v); else p->v = b;
+    }
+    __device__ __forceinline__ static void store_nearest(bf16sr_t *p, float v) { p->v = (bf16_t)v; }
 };
 
 // FP64 read of a stored value (gathers and diagnostics report in FP64).
@@ -72,15 +132,16 @@ __device__ __forceinline__ double load_f64(const S *p)
     return (double)Codec<S>::load(p);
 }
 
-// Store of an FP64 value: rounded once, directly from FP64, for FP64 and
-// FP32 storage; FP16/BF16 go through FP32 first.
+// Store of an FP64 value (initial state, checkpoint): rounded once,
+// directly from FP64, for FP64 and FP32 storage; FP16/BF16 go through FP32
+// first and round to nearest in every variant.
 template <class S>
 __device__ __forceinline__ void store_f64(S *p, double v)
 {
     if constexpr (sizeof(S) >= 4)
         *p = (S)v;
     else
-        Codec<S>::template store<false>(p, (float)v);
+        Codec<S>::store_nearest(p, (float)v);
 }
 
 } // namespace ptrt

@@ -32,6 +32,8 @@ inline int dispatch_storage(int storage, bool mask, F &&f)
     case PTRT_F32: return with_mask(Tag<float>{});
     case PTRT_F16: return with_mask(Tag<_Float16>{});
     case PTRT_BF16: return with_mask(Tag<bf16_t>{});
+    case PTRT_F16_SR: return with_mask(Tag<f16sr_t>{});
+    case PTRT_BF16_SR: return with_mask(Tag<bf16sr_t>{});
     default: return PTRT_EINVAL;
     }
 }
@@ -50,6 +52,8 @@ inline int dispatch(int lattice, int storage, bool mask, F &&f)
         case PTRT_F32: return with_mask(Tag<float>{});
         case PTRT_F16: return with_mask(Tag<_Float16>{});
         case PTRT_BF16: return with_mask(Tag<bf16_t>{});
+        case PTRT_F16_SR: return with_mask(Tag<f16sr_t>{});
+        case PTRT_BF16_SR: return with_mask(Tag<bf16sr_t>{});
         default: return PTRT_EINVAL;
         }
     };
@@ -65,7 +69,9 @@ inline size_t storage_bytes(int storage)
     case PTRT_F64: return 8;
     case PTRT_F32: return 4;
     case PTRT_F16:
-    case PTRT_BF16: return 2;
+    case PTRT_BF16:
+    case PTRT_F16_SR:
+    case PTRT_BF16_SR: return 2;
     default: return 0;
     }
 }

@@ -665,6 +665,10 @@ struct NonFiniteBits<bf16_t> {
     using W = unsigned short;
     static constexpr W mask = 0x7F80u;
 };
+template <>
+struct NonFiniteBits<f16sr_t> : NonFiniteBits<_Float16> {};
+template <>
+struct NonFiniteBits<bf16sr_t> : NonFiniteBits<bf16_t> {};
 
 template <class S>
 __global__ void __launch_bounds__(256)

@@ -185,7 +185,7 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
         // measured against one step per pass: a gain at every size in FP32
         // and FP64 (64^2 ... 4096^2, 8 - 30 %); none in FP16 / BF16, whose
         // one-step kernel moves half the bytes for the same arithmetic
-        if (a.storage == PTRT_F16 || a.storage == PTRT_BF16) return false;
+        if (storage_bytes(a.storage) == 2) return false;
         // with solids: the rows near solids take the masked kernel in a
         // second launch, slower per node than one step per pass, so the
         // pass is used from 2^20 nodes on while they are at most 30 % of

@@ -20,11 +20,12 @@ import torch  # noqa: F401  (must precede loading libptrt.so, see above)
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptrt.so")
 
 PTRT_D2Q9, PTRT_D3Q19, PTRT_D3Q27 = 0, 1, 2
-PTRT_F64, PTRT_F32, PTRT_F16, PTRT_BF16 = 0, 1, 2, 3
+PTRT_F64, PTRT_F32, PTRT_F16, PTRT_BF16, PTRT_F16_SR, PTRT_BF16_SR = 0, 1, 2, 3, 4, 5
 PTRT_MODEL_PTRT, PTRT_MODEL_TRT_RLB, PTRT_MODEL_TRT, PTRT_MODEL_PTRT_EXACT = 0, 1, 2, 3
 MODEL = {"ptrt": PTRT_MODEL_PTRT, "trt-rlb": PTRT_MODEL_TRT_RLB, "trt": PTRT_MODEL_TRT,
          "ptrt-exact": PTRT_MODEL_PTRT_EXACT}
-STORAGE = {"f64": PTRT_F64, "f32": PTRT_F32, "f16": PTRT_F16, "bf16": PTRT_BF16}
+STORAGE = {"f64": PTRT_F64, "f32": PTRT_F32, "f16": PTRT_F16, "bf16": PTRT_BF16,
+           "f16sr": PTRT_F16_SR, "bf16sr": PTRT_BF16_SR}
 PTRT_FORCING_SCHEME2, PTRT_FORCING_SCHEME2_G, PTRT_FORCING_GUO = 0, 1, 2
 FORCING = {"scheme2": PTRT_FORCING_SCHEME2, "scheme2+g": PTRT_FORCING_SCHEME2_G,
            "guo": PTRT_FORCING_GUO}

@@ -74,6 +74,8 @@ def test_state_errors_without_device():
         assert ei.value.code == -1
         with pytest.raises(P.PtrtError):
             P.ptrt_set_storage(h, 9)
+        with pytest.raises(P.PtrtError):
+            P.ptrt_set_storage(h, 6)
         assert P.ptrt_get_time(h) == 0
         assert P.ptrt_bytes_per_node(h) == 2 * 19 * 4
     finally:
@@ -126,7 +128,7 @@ def test_long_rows_below_the_limit_accepted():
     type (nothing is allocated before init)."""
     h = P.ptrt_create(0, 1 << 28, 1, 1, 0.7, 0.25)
     try:
-        for st in (0, 2, 3, 1):
+        for st in (0, 2, 3, 4, 5, 1):
             P.ptrt_set_storage(h, st)
     finally:
         P.ptrt_destroy(h)

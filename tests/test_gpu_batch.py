@@ -47,7 +47,7 @@ def _single(spec, storage, rho, u, steps):
         return L.populations()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16sr"])
 def test_batch_bitwise_equals_single(storage):
     print_case("batch bitwise vs single", storage)
     specs = _small_specs()
