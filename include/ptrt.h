@@ -49,11 +49,13 @@
  * Storage: populations are kept on the GPU as shifted values
  * f_i - w_i (reference density 1) in the storage type chosen with
  * ptrt_set_storage: FP64 (FP64 arithmetic), FP32, FP16 or BF16 (FP32
- * arithmetic; FP16/BF16 round to nearest even on store).
+ * arithmetic; FP16/BF16 round to nearest even on store, or stochastically
+ * in their _SR variants).
  *
  * Streams: work is enqueued on the stream given to ptrt_set_stream (default:
  * the null stream).  ptrt_step is asynchronous; the calls that return host
- * data synchronise that stream.
+ * data synchronise that stream.  Work already enqueued on an earlier stream
+ * is not waited for when the stream changes: the caller orders the two.
  *
  * Errors: every int-returning call returns PTRT_OK (0) or a negative code and
  * leaves a message readable with ptrt_last_error.  A handle is not

@@ -164,11 +164,19 @@ int bfail(ptrt_batch *b, int code, const std::string &msg)
     return code;
 }
 
+// A failed HIP call (see fail_hip of the single-lattice handle): its error
+// is also taken off the thread's last-error slot.
+int bfail_hip(ptrt_batch *b, int code, const std::string &msg)
+{
+    (void)hipGetLastError();
+    return bfail(b, code, msg);
+}
+
 #define BHIPCHK(b, expr)                                                                      \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
         if (e_ != hipSuccess)                                                                 \
-            return bfail((b), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return bfail_hip((b), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
 void drop_graphs(ptrt_batch *b)
@@ -185,6 +193,24 @@ bool valid_plan(int tx, int ty)
     const int n = tx * ty;
     return tx >= 32 && ty >= 1 && tx % 32 == 0 && (ty > 1 || tx % 64 == 0) &&
            (n == 64 || n == 128 || n == 256 || n == 512 || n == 1024);
+}
+
+// A task or tile table in a new device allocation (*out; nothing is
+// allocated on failure), so that the table in use is replaced only once
+// its successor is complete.
+int upload_table(ptrt_batch *b, const std::vector<int4> &table, int4 **out)
+{
+    *out = nullptr;
+    int4 *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(int4) * std::max<size_t>(1, table.size()));
+    if (e != hipSuccess) return bfail_hip(b, PTRT_ENOMEM, std::string("hipMalloc of a task table: ") + hipGetErrorString(e));
+    if (!table.empty()) e = hipMemcpy(d, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return bfail_hip(b, PTRT_EDEVICE, std::string("task table upload: ") + hipGetErrorString(e));
+    }
+    *out = d;
+    return PTRT_OK;
 }
 
 int build_tiles(ptrt_batch *b)
@@ -227,10 +253,11 @@ int build_tiles(ptrt_batch *b)
     } else {
         table = spatial;
     }
-    if (b->d_tiles) hipFree(b->d_tiles);
-    b->d_tiles = nullptr;
-    BHIPCHK(b, hipMalloc(&b->d_tiles, sizeof(int4) * (size_t)n));
-    BHIPCHK(b, hipMemcpy(b->d_tiles, table.data(), sizeof(int4) * (size_t)n, hipMemcpyHostToDevice));
+    int4 *fresh = nullptr;
+    const int rc = upload_table(b, table, &fresh);
+    if (rc != PTRT_OK) return rc; // the previous table stays in use
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_tiles = fresh;
     b->ntiles = n;
     drop_graphs(b);
     return PTRT_OK;
@@ -368,13 +395,15 @@ int build_tasks2(ptrt_batch *b)
             }
         }
     }
-    b->n_plain2 = (int)plain.size();
-    b->n_masked2 = (int)masked.size();
+    const int n_plain = (int)plain.size(), n_masked = (int)masked.size();
     plain.insert(plain.end(), masked.begin(), masked.end());
+    int4 *fresh = nullptr;
+    const int rc = upload_table(b, plain, &fresh);
+    if (rc != PTRT_OK) return rc; // the previous table stays in use
     if (b->d_tasks2) (void)hipFree(b->d_tasks2);
-    b->d_tasks2 = nullptr;
-    BHIPCHK(b, hipMalloc(&b->d_tasks2, sizeof(int4) * plain.size()));
-    BHIPCHK(b, hipMemcpy(b->d_tasks2, plain.data(), sizeof(int4) * plain.size(), hipMemcpyHostToDevice));
+    b->d_tasks2 = fresh;
+    b->n_plain2 = n_plain;
+    b->n_masked2 = n_masked;
     // non-temporal stores once the two state buffers exceed the 256 MB
     // last-level cache (as for a single lattice)
     b->nt = 2.0 * (double)b->total_elems * (double)storage_bytes(b->storage) > 256.0 * 1024 * 1024;
@@ -392,12 +421,12 @@ int capture_graph(ptrt_batch *b, int parity)
     hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
     b->graph_flip[parity] = b->cur ^ parity;
     b->cur = saved;
-    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bfail_hip(b, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph[parity], g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) {
         b->graph[parity] = nullptr;
-        return bfail(b, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        return bfail_hip(b, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
     return PTRT_OK;
 }
@@ -481,7 +510,7 @@ int autotune2(ptrt_batch *b, hipEvent_t e0, hipEvent_t e1)
                         if (pers && b->blocks2 == 0) continue;
                         b->conc2 = conc;
                         const float ms = time_passes2(b, e0, e1, 10);
-                        if (ms < 0) return bfail(b, PTRT_EDEVICE, "two-step autotune timing failed");
+                        if (ms < 0) return bfail_hip(b, PTRT_EDEVICE, "two-step autotune timing failed");
                         tried.push_back({yc, ym, nw, b->blocks2, conc, ms});
                     }
         }
@@ -503,7 +532,7 @@ int autotune2(ptrt_batch *b, hipEvent_t e0, hipEvent_t e1)
         float t[3];
         for (float &x : t) {
             x = time_passes2(b, e0, e1, 10);
-            if (x < 0) return bfail(b, PTRT_EDEVICE, "two-step autotune timing failed");
+            if (x < 0) return bfail_hip(b, PTRT_EDEVICE, "two-step autotune timing failed");
         }
         std::sort(t, t + 3);
         if (t[1] < best_med) {
@@ -585,6 +614,7 @@ int ptrt_batch_create(int count, const ptrt_instance_desc *desc, int storage, pt
     b->mask_bytes = moff;
 
     auto cleanup = [&](int code, const std::string &msg) {
+        (void)hipGetLastError(); // reported here (see bfail_hip)
         g_batch_create_error = msg;
         ptrt_batch_destroy(b);
         return code;
@@ -678,7 +708,7 @@ int ptrt_batch_init_equilibrium(ptrt_batch *b, int k, const double *rho, const d
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     hipFree(d_in);
-    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("init: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bfail_hip(b, PTRT_EDEVICE, std::string("init: ") + hipGetErrorString(e));
     return PTRT_OK;
 }
 
@@ -687,11 +717,19 @@ int ptrt_batch_set_plan(ptrt_batch *b, int tile_x, int tile_y, int blocks, int x
     if (!b) return PTRT_EINVAL;
     if (!valid_plan(tile_x, tile_y) || blocks < 0) return bfail(b, PTRT_EINVAL, "invalid tile plan");
     BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const int old[4] = {b->tile_x, b->tile_y, b->blocks, b->xcd_order};
     b->tile_x = tile_x;
     b->tile_y = tile_y;
     b->blocks = blocks;
     b->xcd_order = xcd_order ? 1 : 0;
-    return build_tiles(b);
+    const int rc = build_tiles(b);
+    if (rc != PTRT_OK) { // the previous plan and its table stay
+        b->tile_x = old[0];
+        b->tile_y = old[1];
+        b->blocks = old[2];
+        b->xcd_order = old[3];
+    }
+    return rc;
 }
 
 int ptrt_batch_step(ptrt_batch *b, int n)
@@ -769,12 +807,21 @@ int ptrt_batch_set_plan2(ptrt_batch *b, int rows, int masked_rows, int waves, in
     if (b->storage != PTRT_F32 && b->storage != PTRT_F64)
         return bfail(b, PTRT_ESTATE, "the two-step pass runs in FP32 and FP64 storage only");
     BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const int old[5] = {b->yc2, b->ym2, b->nw2, b->blocks2, b->conc2};
     b->yc2 = rows;
     b->ym2 = masked_rows;
     b->nw2 = waves;
     b->blocks2 = blocks;
     b->conc2 = concurrent ? 1 : 0;
-    return build_tasks2(b);
+    const int rc = build_tasks2(b);
+    if (rc != PTRT_OK) { // the previous plan and its table stay
+        b->yc2 = old[0];
+        b->ym2 = old[1];
+        b->nw2 = old[2];
+        b->blocks2 = old[3];
+        b->conc2 = old[4];
+    }
+    return rc;
 }
 
 int ptrt_batch_get_plan2(const ptrt_batch *b, int plan_out[5])
@@ -805,7 +852,7 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = 1e30f;
     int bt[4] = {b->tile_x, b->tile_y, b->blocks, b->xcd_order};
-    int rc = e == hipSuccess ? PTRT_OK : bfail(b, PTRT_EDEVICE, "autotune setup failed");
+    int rc = e == hipSuccess ? PTRT_OK : bfail_hip(b, PTRT_EDEVICE, "autotune setup failed");
     for (const auto &sh : shapes) {
         if (rc != PTRT_OK) break;
         for (int gsz : grids)
@@ -817,7 +864,7 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
                 for (int k = 0; k < 14; ++k) launch_fused_any(b, b->stream);
                 hipEventRecord(e1, b->stream);
                 if (hipEventSynchronize(e1) != hipSuccess) {
-                    rc = bfail(b, PTRT_EDEVICE, "autotune timing failed");
+                    rc = bfail_hip(b, PTRT_EDEVICE, "autotune timing failed");
                     break;
                 }
                 float ms = 0.f;
@@ -841,7 +888,7 @@ int ptrt_batch_autotune(ptrt_batch *b, int *tx_o, int *ty_o, int *blocks_o, int 
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     hipFree(saved);
     if (rc != PTRT_OK) return rc;
-    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("autotune restore: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bfail_hip(b, PTRT_EDEVICE, std::string("autotune restore: ") + hipGetErrorString(e));
     rc = ptrt_batch_set_plan(b, bt[0], bt[1], bt[2], bt[3]);
     if (tx_o) *tx_o = bt[0];
     if (ty_o) *ty_o = bt[1];
@@ -882,7 +929,7 @@ static int batch_download(ptrt_batch *b, int k, double *rho, double *u, double *
         e = hipMemcpyAsync(f, d_f, sizeof(double) * 9 * h.N, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     hipFree(d_out);
-    if (e != hipSuccess) return bfail(b, PTRT_EDEVICE, std::string("download: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bfail_hip(b, PTRT_EDEVICE, std::string("download: ") + hipGetErrorString(e));
     if (u) std::memset(u + 2 * h.N, 0, sizeof(double) * h.N);
     return PTRT_OK;
 }

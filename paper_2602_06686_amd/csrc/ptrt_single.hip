@@ -86,11 +86,20 @@ int fail(ptrt_ctx *c, int code, const std::string &msg)
     return code;
 }
 
+// A failed HIP call, reported here: its error is also taken off the
+// thread's last-error slot, so that a later launch check (hipGetLastError)
+// does not report it a second time as its own.
+int fail_hip(ptrt_ctx *c, int code, const std::string &msg)
+{
+    (void)hipGetLastError();
+    return fail(c, code, msg);
+}
+
 #define HIPCHK(c, expr)                                                                      \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
         if (e_ != hipSuccess)                                                                \
-            return fail((c), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return fail_hip((c), PTRT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
 // f(bool_constant<OPEN>) for the handle's x boundaries (open ones exist on
@@ -122,9 +131,41 @@ int slab_planes(const ptrt_ctx *c, int per_node_doubles)
 
 int ensure_phi(ptrt_ctx *c, int forcing);
 
+// Free what allocate_device has allocated (after a failure part way, so
+// that the next attempt starts from nothing).
+void release_device(ptrt_ctx *c)
+{
+    for (void *&p : c->buf)
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    void **owned[] = {(void **)&c->d_mask, (void **)&c->d_near, (void **)&c->d_tasks,
+                      (void **)&c->d_partials, (void **)&c->d_red};
+    for (void **p : owned)
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    c->n_plain = c->n_special = 0;
+}
+
+int allocate_device(ptrt_ctx *c);
+
 int ensure_allocated(ptrt_ctx *c)
 {
     if (c->allocated) return PTRT_OK;
+    const int rc = allocate_device(c);
+    if (rc != PTRT_OK) {
+        release_device(c);
+        return rc;
+    }
+    c->allocated = true;
+    return ensure_phi(c, c->forcing);
+}
+
+int allocate_device(ptrt_ctx *c)
+{
     const size_t elem = storage_bytes(c->storage);
     c->elems = make_layout(c->Q, c->nx, c->ny, c->nz, elem, c->geo);
     const size_t bytes = (size_t)c->elems * elem;
@@ -139,7 +180,7 @@ int ensure_allocated(ptrt_ctx *c)
         hipError_t e = hipMalloc(&c->buf[k], bytes);
         if (e != hipSuccess) {
             c->buf[k] = nullptr;
-            return fail(c, PTRT_ENOMEM, std::string("hipMalloc of populations: ") + hipGetErrorString(e));
+            return fail_hip(c, PTRT_ENOMEM, std::string("hipMalloc of populations: ") + hipGetErrorString(e));
         }
         HIPCHK(c, hipMemset(c->buf[k], 0, bytes));
     }
@@ -227,8 +268,7 @@ int ensure_allocated(ptrt_ctx *c)
     c->nparts = gg.x * gg.y * gg.z;
     HIPCHK(c, hipMalloc(&c->d_partials, sizeof(double2) * (size_t)c->nparts));
     HIPCHK(c, hipMalloc(&c->d_red, 2 * sizeof(double)));
-    c->allocated = true;
-    return ensure_phi(c, c->forcing);
+    return PTRT_OK;
 }
 
 Geom geom(const ptrt_ctx *c) { return c->geo; }
@@ -269,7 +309,7 @@ int upload_state(ptrt_ctx *c, const double *rho, const double *u, const double *
             }
         }
         if (e != hipSuccess) {
-            rc = fail(c, PTRT_EDEVICE, std::string("host to device copy: ") + hipGetErrorString(e));
+            rc = fail_hip(c, PTRT_EDEVICE, std::string("host to device copy: ") + hipGetErrorString(e));
             break;
         }
         const Geom g = geom(c);
@@ -292,7 +332,7 @@ int upload_state(ptrt_ctx *c, const double *rho, const double *u, const double *
         });
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) rc = fail(c, PTRT_EDEVICE, std::string("state upload: ") + hipGetErrorString(e));
+        if (e != hipSuccess) rc = fail_hip(c, PTRT_EDEVICE, std::string("state upload: ") + hipGetErrorString(e));
     }
     (void)hipFree(d_in);
     return rc;
@@ -346,7 +386,7 @@ int download_state(ptrt_ctx *c, double *rho, double *u, double *f)
                                    cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
-            rc = fail(c, PTRT_EDEVICE, std::string("state download: ") + hipGetErrorString(e));
+            rc = fail_hip(c, PTRT_EDEVICE, std::string("state download: ") + hipGetErrorString(e));
             break;
         }
     }
@@ -435,7 +475,7 @@ int ensure_phi(ptrt_ctx *c, int forcing)
     hipError_t e = hipMalloc(&c->d_phi, phi_bytes(c));
     if (e != hipSuccess) {
         c->d_phi = nullptr;
-        return fail(c, PTRT_ENOMEM, std::string("hipMalloc of the Phi field: ") + hipGetErrorString(e));
+        return fail_hip(c, PTRT_ENOMEM, std::string("hipMalloc of the Phi field: ") + hipGetErrorString(e));
     }
     return PTRT_OK;
 }
@@ -461,12 +501,12 @@ int capture_graph(ptrt_ctx *c, int parity)
     launch_steps(c, c->capture_stream, GRAPH_STEPS);
     hipError_t e = hipStreamEndCapture(c->capture_stream, &gr);
     c->cur = saved;
-    if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail_hip(c, PTRT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&c->graph[parity], gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     if (e != hipSuccess) {
         c->graph[parity] = nullptr;
-        return fail(c, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        return fail_hip(c, PTRT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
     return PTRT_OK;
 }
@@ -536,7 +576,7 @@ int reset_check(ptrt_ctx *c)
 {
     c->bad_pending = false;
     c->diverged_at = -1;
-    if (!c->d_bad) return PTRT_OK;
+    if (!c->d_bad || !c->h_bad || !c->bad_event) return PTRT_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemset(c->d_bad, 0xFF, sizeof(unsigned long long)));
     *c->h_bad = NO_STEP;
@@ -662,7 +702,7 @@ int ptrt_set_model(ptrt_ctx *c, int model)
     if (c->forcing != FORCE_II && model != MODEL_PTRT && model != MODEL_PTRT_EXACT)
         return fail(c, PTRT_EINVAL, "the comparison models use the default forcing only");
     if (hipStreamSynchronize(c->stream) != hipSuccess)
-        return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
+        return fail_hip(c, PTRT_EDEVICE, "stream synchronisation failed");
     c->model = model;
     drop_graphs(c);
     return PTRT_OK;
@@ -692,11 +732,9 @@ int ptrt_momentum_exchange(ptrt_ctx *c, double force_out[3])
         return fail(c, PTRT_ESTATE, "momentum exchange needs a completed step");
     for (int a = 0; a < 3; ++a) force_out[a] = 0.0;
     if (!c->has_mask) return PTRT_OK;
-    if (!c->d_force_parts) {
-        const size_t nparts = momentum_parts(c);
-        HIPCHK(c, hipMalloc(&c->d_force_parts, 3 * sizeof(double) * nparts));
-        HIPCHK(c, hipMalloc(&c->d_force, 3 * sizeof(double)));
-    }
+    if (!c->d_force_parts)
+        HIPCHK(c, hipMalloc(&c->d_force_parts, 3 * sizeof(double) * momentum_parts(c)));
+    if (!c->d_force) HIPCHK(c, hipMalloc(&c->d_force, 3 * sizeof(double)));
     return momentum_exchange_with(c, c->d_force_parts, c->d_force, force_out);
 }
 
@@ -734,7 +772,7 @@ int ptrt_set_steps_per_pass(ptrt_ctx *c, int steps)
     if (!c) return PTRT_EINVAL;
     if (steps != 1 && steps != 2) return fail(c, PTRT_EINVAL, "steps per pass must be 1 or 2");
     if (c->allocated && hipStreamSynchronize(c->stream) != hipSuccess)
-        return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
+        return fail_hip(c, PTRT_EDEVICE, "stream synchronisation failed");
     c->steps_per_pass = steps;
     drop_graphs(c);
     return PTRT_OK;
@@ -752,7 +790,7 @@ int ptrt_set_forcing(ptrt_ctx *c, int forcing)
     if (forcing != FORCE_II && !c->row_kernel)
         return fail(c, PTRT_EINVAL, "forcing variants need ny and nz <= 65535");
     if (c->allocated && hipStreamSynchronize(c->stream) != hipSuccess)
-        return fail(c, PTRT_EDEVICE, "stream synchronisation failed");
+        return fail_hip(c, PTRT_EDEVICE, "stream synchronisation failed");
     const int rc = ensure_phi(c, forcing);
     if (rc != PTRT_OK) return rc; // scheme unchanged
     c->forcing = forcing;
@@ -818,7 +856,7 @@ int ptrt_step(ptrt_ctx *c, int n)
         }
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(c, PTRT_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail_hip(c, PTRT_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return PTRT_OK;
 }
 
@@ -871,11 +909,11 @@ int ptrt_set_divergence_check(ptrt_ctx *c, int every)
 {
     if (!c) return PTRT_EINVAL;
     if (every < 0) return fail(c, PTRT_EINVAL, "the check interval must be >= 0");
-    if (every > 0 && !c->d_bad) {
-        HIPCHK(c, hipMalloc(&c->d_bad, sizeof(unsigned long long)));
+    // each part allocated once (a failed attempt leaves the others for the next)
+    if (every > 0 && !c->d_bad) HIPCHK(c, hipMalloc(&c->d_bad, sizeof(unsigned long long)));
+    if (every > 0 && !c->h_bad)
         HIPCHK(c, hipHostMalloc((void **)&c->h_bad, sizeof(unsigned long long), hipHostMallocDefault));
-        HIPCHK(c, hipEventCreateWithFlags(&c->bad_event, hipEventDisableTiming));
-    }
+    if (every > 0 && !c->bad_event) HIPCHK(c, hipEventCreateWithFlags(&c->bad_event, hipEventDisableTiming));
     const int rc = reset_check(c);
     if (rc != PTRT_OK) return rc;
     c->check_every = every;
