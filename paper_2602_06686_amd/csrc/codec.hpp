@@ -2,7 +2,11 @@
 // conversion to the compute type.  FP16 and BF16 round to nearest even;
 // their stochastic-rounding variants (f16sr_t, bf16sr_t: the same bits in
 // memory) round each store up or down with the probability given by its
-// distance to the two neighbours.
+// distance to the two neighbours.  fast_recip: the collision takes 1 / rho
+// from the refined hardware reciprocal (FP32 storage, whose two-step passes
+// are bound by instruction issue); the 16-bit types keep the correctly
+// rounded division (their one-step kernels are bound by HBM, and their
+// rounding stays as measured for the precision form).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +22,7 @@ struct Codec;
 template <>
 struct Codec<double> {
     using compute = double;
+    static constexpr bool fast_recip = false;
     static constexpr int bytes = 8;
     __device__ __forceinline__ static double load(const double *p) { return *p; }
     __device__ __forceinline__ static double to_double(double v) { return v; }
@@ -31,6 +36,7 @@ struct Codec<double> {
 template <>
 struct Codec<float> {
     using compute = float;
+    static constexpr bool fast_recip = true;
     static constexpr int bytes = 4;
     __device__ __forceinline__ static float load(const float *p) { return *p; }
     template <bool NT = false>
@@ -43,6 +49,7 @@ struct Codec<float> {
 template <>
 struct Codec<_Float16> {
     using compute = float;
+    static constexpr bool fast_recip = false;
     static constexpr int bytes = 2;
     __device__ __forceinline__ static float load(const _Float16 *p) { return (float)*p; }
     template <bool NT = false>
@@ -57,6 +64,7 @@ struct Codec<_Float16> {
 template <>
 struct Codec<bf16_t> {
     using compute = float;
+    static constexpr bool fast_recip = false;
     static constexpr int bytes = 2;
     __device__ __forceinline__ static float load(const bf16_t *p) { return (float)*p; }
     // the conversion compiles to the gfx950 float -> bf16 instruction, which
@@ -100,6 +108,7 @@ struct bf16sr_t {
 template <>
 struct Codec<f16sr_t> {
     using compute = float;
+    static constexpr bool fast_recip = false;
     static constexpr int bytes = 2;
     __device__ __forceinline__ static float load(const f16sr_t *p) { return (float)p->v; }
     template <bool NT = false>
@@ -114,6 +123,7 @@ struct Codec<f16sr_t> {
 template <>
 struct Codec<bf16sr_t> {
     using compute = float;
+    static constexpr bool fast_recip = false;
     static constexpr int bytes = 2;
     __device__ __forceinline__ static float load(const bf16sr_t *p) { return (float)p->v; }
     template <bool NT = false>

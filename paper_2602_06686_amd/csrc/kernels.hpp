@@ -299,14 +299,15 @@ __device__ __forceinline__ void node_update(const S *__restrict__ src, S *__rest
     Src<C> sc{};
     if constexpr (FORCING == FORCE_II_G) sc = phi_differences<L, C>(phi, g, r, x, y, z, row);
     C rho, ux, uy, uz;
+    constexpr bool FR = Codec<S>::fast_recip;
     if constexpr (MODEL == MODEL_TRT_RLB)
-        collide_trt_rlb<L, C>(h, r, rho, ux, uy, uz);
+        collide_trt_rlb<L, C, FR>(h, r, rho, ux, uy, uz);
     else if constexpr (MODEL == MODEL_TRT)
-        collide<L, C, false, FORCING>(h, r, rho, ux, uy, uz, sc);
+        collide<L, C, false, FORCING, FR>(h, r, rho, ux, uy, uz, sc);
     else if constexpr (L::Q == 27)
-        collide_d3q27<C, MODEL == MODEL_PTRT_EXACT, FORCING>(h, r, rho, ux, uy, uz, sc);
+        collide_d3q27<C, MODEL == MODEL_PTRT_EXACT, FORCING, FR>(h, r, rho, ux, uy, uz, sc);
     else
-        collide<L, C, true, FORCING>(h, r, rho, ux, uy, uz, sc);
+        collide<L, C, true, FORCING, FR>(h, r, rho, ux, uy, uz, sc);
     static_for<L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         Codec<S>::template store<NT>(at(dst, g, i, row, x), h[i]);

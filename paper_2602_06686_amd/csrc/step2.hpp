@@ -98,18 +98,19 @@ __device__ __forceinline__ void lds_barrier()
 // Collision of a pass: P-TRT (the hybrid of Eq. PTRT_D3Q27 on D3Q27), or
 // for the efficiency comparison TRT-RLB (Eq. TRT-RLB) or standard TRT, the
 // same functions as in the one-step kernel (default forcing).
-template <class L, class C, int MODEL = MODEL_PTRT>
+template <class L, class S, int MODEL = MODEL_PTRT, class C = typename Codec<S>::compute>
 __device__ __forceinline__ void collide_pass(C (&h)[L::Q], const Coef<L, C> &r, C &rho, C &ux,
                                              C &uy, C &uz)
 {
+    constexpr bool FR = Codec<S>::fast_recip;
     if constexpr (MODEL == MODEL_TRT_RLB)
-        collide_trt_rlb<L, C>(h, r, rho, ux, uy, uz);
+        collide_trt_rlb<L, C, FR>(h, r, rho, ux, uy, uz);
     else if constexpr (MODEL == MODEL_TRT)
-        collide<L, C, false>(h, r, rho, ux, uy, uz);
+        collide<L, C, false, FORCE_II, FR>(h, r, rho, ux, uy, uz);
     else if constexpr (L::Q == 27)
-        collide_d3q27<C, false>(h, r, rho, ux, uy, uz);
+        collide_d3q27<C, false, FORCE_II, FR>(h, r, rho, ux, uy, uz);
     else
-        collide<L, C, true>(h, r, rho, ux, uy, uz);
+        collide<L, C, true, FORCE_II, FR>(h, r, rho, ux, uy, uz);
 }
 
 // One column chunk of the pass, run by the workgroup: second steps for
@@ -204,7 +205,7 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
             h[i] = Codec<S>::load(&raw[i]);
         });
         C rho, ux, uy, uz;
-        collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
+        collide_pass<L, S, MODEL>(h, r, rho, ux, uy, uz);
         if (!valid) return;
         const int a = ay * AX + ax;
         static_for<L::Q>([&](auto ic) {
@@ -326,7 +327,7 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
                 });
             }
             C rho, ux, uy, uz;
-            collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
+            collide_pass<L, S, MODEL>(h, r, rho, ux, uy, uz);
             if (store) {
                 static_for<L::Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
@@ -538,7 +539,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
         });
         if constexpr (OPEN) open_fix(h, ax);
         C rho, ux, uy, uz;
-        collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
+        collide_pass<L, S, MODEL>(h, r, rho, ux, uy, uz);
         static_for<L::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int c = K::cls(i);
@@ -583,7 +584,7 @@ step2_2d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
             });
             if constexpr (OPEN) open_fix(h, bxg);
             C rho, ux, uy, uz;
-            collide_pass<L, C, MODEL>(h, r, rho, ux, uy, uz);
+            collide_pass<L, S, MODEL>(h, r, rho, ux, uy, uz);
             char *db = reinterpret_cast<char *>(dst) + o[1];
             static_for<L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;

@@ -37,14 +37,14 @@ struct Herm {
     static constexpr double xyz = ex * ey * ez;
 };
 
-template <class L, class C>
+template <class L, class C, bool FAST = false>
 __device__ __forceinline__ void collide_trt_rlb(C (&h)[L::Q], const Coef<L, C> &r, C &rho_o,
                                                 C &ux_o, C &uy_o, C &uz_o)
 {
     C drho, jx, jy, jz;
     shifted_moments<L>(h, drho, jx, jy, jz);
     const C rho = C(1) + drho;
-    const C inv = C(1) / rho;
+    const C inv = recip<FAST>(rho);
     const C ux = jx * inv + r.hgx;
     const C uy = jy * inv + r.hgy;
     const C uz = jz * inv + r.hgz;
