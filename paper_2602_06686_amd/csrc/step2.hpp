@@ -119,7 +119,7 @@ __device__ __forceinline__ void collide_pass(C (&h)[L::Q], const Coef<L, C> &r, 
 // steps (the first step pulls through pull<L, S, true>; the second takes
 // the node's own first-step value of the opposite direction where the
 // source node is solid, and solid nodes are not stored).
-template <class L, class S, bool NT, bool MASK, int MODEL = MODEL_PTRT>
+template <class L, class S, bool NT, bool MASK, int MODEL = MODEL_PTRT, bool ZOFF = false>
 __device__ __forceinline__ void
 step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
               const Geom &g, const Coef<L, typename Codec<S>::compute> &r, S *lds, int x0, int y0,
@@ -195,6 +195,39 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
             raw[i] = *reinterpret_cast<const S *>(p);
         });
     };
+    // ZOFF: the source offsets of a task's pulls inside a z plane stay the
+    // same all the way up the column (the lane's node moves in z only), so
+    // they are formed once; a pull is then the scalar base of its source
+    // plane plus that 32-bit lane offset (step2_zoff_ok: a z plane is a
+    // whole number of row tiles, below 2^32 bytes).  Measured in FP32:
+    // 1017 -> 790 VALU instructions per plane and wave, +3-6 % at 256^3 -
+    // 512^3.  FP64 keeps load_row (its registers are all in use).
+    static_assert(!ZOFF || (sizeof(S) == 4 && !MASK), "source offsets: FP32 without solids");
+    const long long zstride = (long long)(g.ny >> g.lr) * g.tile * (long long)sizeof(S);
+    auto make_off = [&](int task, auto &off) {
+        int ax, ay;
+        a_node(task, ax, ay);
+        const int gx = wrapc(x0 - 1 + ax, g.nx), gy = wrapc(y0 - 1 + ay, g.ny);
+        const unsigned m = (1u << g.lr) - 1u;
+        static_for<L::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int sx = wrapc(gx - L::ex(i), g.nx), sy = wrapc(gy - L::ey(i), g.ny);
+            off[i] = ((unsigned)(sy >> g.lr) * (unsigned)g.tile + (unsigned)i * (unsigned)g.plane +
+                      ((unsigned)sy & m) * (unsigned)g.pitch + (unsigned)sx) *
+                     (unsigned)sizeof(S);
+        });
+    };
+    auto load_off = [&](const auto &off, int k, S (&raw)[L::Q]) {
+        const int gz = wrapc(k, g.nz);
+        const int zm = gz == 0 ? g.nz - 1 : gz - 1, zp = gz == g.nz - 1 ? 0 : gz + 1;
+        const char *sb = reinterpret_cast<const char *>(src);
+        const char *base[3] = {sb + (long long)zm * zstride, sb + (long long)gz * zstride,
+                               sb + (long long)zp * zstride};
+        static_for<L::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            raw[i] = *reinterpret_cast<const S *>(base[1 - L::ez(i)] + off[i]);
+        });
+    };
     // part 2: collide and keep the result in the class slots of plane `it`
     auto finish_a = [&](int task, int it, const S (&raw)[L::Q]) {
         int ax, ay;
@@ -222,6 +255,11 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
     const int t0 = w, t1 = w + BY;
     const bool has1 = t1 <= AY;
     S raw0[L::Q], raw1[L::Q];
+    unsigned off0[ZOFF ? L::Q : 1], off1[ZOFF ? L::Q : 1];
+    if constexpr (ZOFF) {
+        make_off(t0, off0);
+        make_off(t1, off1);
+    }
     // FP64 (one workgroup per CU, so no other workgroup's work covers the
     // load latency) keeps the loads of two planes in flight, in a second
     // register set used on alternate planes (loop unrolled by two; measured
@@ -240,6 +278,9 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
                     load_a(t1, k, raw1);
             }
             load_row(t0, k, raw0);
+        } else if constexpr (ZOFF) {
+            if (has1) load_off(off1, k, raw1);
+            load_off(off0, k, raw0);
         } else {
             if (has1) load_a(t1, k, raw1);
             load_a(t0, k, raw0);
@@ -367,8 +408,19 @@ step2_3d_task(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__r
     }
 }
 
+// Per-task source offsets of the first step's pulls (ZOFF in
+// step2_3d_task): FP32, a z plane a whole number of row tiles (ny a
+// multiple of 2^lr, so that a node's row offset splits into a z part and a
+// y part) and below 2^32 bytes (the offsets are 32-bit).
+template <class S>
+inline bool step2_zoff_ok(const Geom &g)
+{
+    if (sizeof(S) != 4 || g.ny % (1 << g.lr) != 0) return false;
+    return (double)(g.ny >> g.lr) * (double)g.tile * (double)sizeof(S) < 4294967296.0;
+}
+
 // Grid (x blocks, y blocks, z chunks of zc planes), without solids.
-template <class L, class S, bool NT, int MODEL = MODEL_PTRT>
+template <class L, class S, bool NT, int MODEL = MODEL_PTRT, bool ZOFF = false>
 __global__ void __launch_bounds__((64 * Step2Shape<L, S>::WAVES))
 k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
         Coef<L, typename Codec<S>::compute> r, int zc)
@@ -378,12 +430,12 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     int bx, by, bz;
     xcd_block(bx, by, bz);
     const int zs = bz * zc;
-    step2_3d_task<L, S, NT, false, MODEL>(src, dst, nullptr, g, r, lds, bx * SH::BX,
-                                          by * SH::BY, zs, min(zs + zc, g.nz));
+    step2_3d_task<L, S, NT, false, MODEL, ZOFF>(src, dst, nullptr, g, r, lds, bx * SH::BX,
+                                                by * SH::BY, zs, min(zs + zc, g.nz));
 }
 
 // Task list (with solids): workgroup t runs tasks[t] = {x0, y0, zs, ze}.
-template <class L, class S, bool NT, bool MASK>
+template <class L, class S, bool NT, bool MASK, bool ZOFF = false>
 __global__ void __launch_bounds__((64 * Step2Shape<L, S, MASK>::WAVES))
 k_step2_list(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__restrict__ mask,
              Geom g, Coef<L, typename Codec<S>::compute> r, const int4 *__restrict__ tasks,
@@ -395,7 +447,8 @@ k_step2_list(const S *__restrict__ src, S *__restrict__ dst, const uint8_t *__re
     xcd_block(t, unused_y, unused_z);
     if (t >= ntasks) return;
     const int4 tk = tasks[t];
-    step2_3d_task<L, S, NT, MASK>(src, dst, mask, g, r, lds, tk.x, tk.y, tk.z, tk.w);
+    step2_3d_task<L, S, NT, MASK, MODEL_PTRT, ZOFF>(src, dst, mask, g, r, lds, tk.x, tk.y, tk.z,
+                                                   tk.w);
 }
 
 // Two fused steps per pass for D2Q9 without solids (the 2D counterpart of

@@ -271,40 +271,57 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                 // on one XCD (measured: HBM reads 1.03x the state)
                 if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * a.g.nz * L::Q * sizeof(S);
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
+                // per-task source offsets where the layout allows (FP32)
+                const bool zoff = step2_zoff_ok<S>(a.g);
+                auto with_zoff = [&](auto f) {
+                    if constexpr (sizeof(S) == 4) {
+                        if (zoff) {
+                            f(std::true_type{});
+                            return;
+                        }
+                    }
+                    f(std::false_type{});
+                };
                 if (a.has_mask) {
                     // the mask-free column chunks, then the masked ones
                     if (pass_bytes) *pass_bytes += (double)a.g.nx * a.g.ny * a.g.nz;
-                    auto go = [&](auto mc, const int4 *list, int n) {
+                    auto go = [&](auto mc, auto zc_, const int4 *list, int n) {
                         constexpr bool M = decltype(mc)::value;
+                        constexpr bool Z = decltype(zc_)::value && !M;
                         if (n == 0) return;
                         const dim3 lblock(64 * Step2Shape<L, S, M>::WAVES, 1, 1);
                         if (a.nt)
-                            hipLaunchKernelGGL((k_step2_list<L, S, true, M>), dim3(n), lblock, 0,
-                                               a.stream, (const S *)a.src, (S *)a.dst, a.mask, a.g,
-                                               r, list, n);
+                            hipLaunchKernelGGL((k_step2_list<L, S, true, M, Z>), dim3(n), lblock,
+                                               0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
+                                               a.g, r, list, n);
                         else
-                            hipLaunchKernelGGL((k_step2_list<L, S, false, M>), dim3(n), lblock, 0,
-                                               a.stream, (const S *)a.src, (S *)a.dst, a.mask, a.g,
-                                               r, list, n);
+                            hipLaunchKernelGGL((k_step2_list<L, S, false, M, Z>), dim3(n), lblock,
+                                               0, a.stream, (const S *)a.src, (S *)a.dst, a.mask,
+                                               a.g, r, list, n);
                     };
-                    go(std::false_type{}, a.tasks_plain, a.n_plain);
-                    go(std::true_type{}, a.tasks_special, a.n_special);
+                    with_zoff([&](auto zc_) {
+                        go(std::false_type{}, zc_, a.tasks_plain, a.n_plain);
+                    });
+                    go(std::true_type{}, std::false_type{}, a.tasks_special, a.n_special);
                 } else {
-                    auto grid_pass = [&](auto modc) {
+                    auto grid_pass = [&](auto modc, auto zc_) {
                         constexpr int MD = decltype(modc)::value;
+                        constexpr bool Z = decltype(zc_)::value;
                         if (a.nt)
-                            hipLaunchKernelGGL((k_step2<L, S, true, MD>), grid, block, 0,
+                            hipLaunchKernelGGL((k_step2<L, S, true, MD, Z>), grid, block, 0,
                                                a.stream, (const S *)a.src, (S *)a.dst, a.g, r, zc);
                         else
-                            hipLaunchKernelGGL((k_step2<L, S, false, MD>), grid, block, 0,
+                            hipLaunchKernelGGL((k_step2<L, S, false, MD, Z>), grid, block, 0,
                                                a.stream, (const S *)a.src, (S *)a.dst, a.g, r, zc);
                     };
-                    if (a.model == MODEL_TRT_RLB)
-                        grid_pass(std::integral_constant<int, MODEL_TRT_RLB>{});
-                    else if (a.model == MODEL_TRT)
-                        grid_pass(std::integral_constant<int, MODEL_TRT>{});
-                    else
-                        grid_pass(std::integral_constant<int, MODEL_PTRT>{});
+                    with_zoff([&](auto zc_) {
+                        if (a.model == MODEL_TRT_RLB)
+                            grid_pass(std::integral_constant<int, MODEL_TRT_RLB>{}, zc_);
+                        else if (a.model == MODEL_TRT)
+                            grid_pass(std::integral_constant<int, MODEL_TRT>{}, zc_);
+                        else
+                            grid_pass(std::integral_constant<int, MODEL_PTRT>{}, zc_);
+                    });
                 }
                 launched = true;
             }

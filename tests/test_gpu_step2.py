@@ -34,6 +34,10 @@ def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5, passes=
         return G.populations()
 
 
+# FP32 D3Q19: where ny is a multiple of the rows per layout tile (16 at
+# nx = 64, 8 at 128, 4 at 192 and 256) the pass forms each task's source
+# offsets once (7x16x128, 4x32x64, 3x64x128, 2x16x192); elsewhere it takes
+# the general pulls
 @pytest.mark.parametrize("lat,storage,shape", [
     (1, "f32", (6, 8, 64)), (1, "f32", (7, 16, 128)), (1, "f32", (2, 8, 64)),
     (1, "f32", (3, 12, 64)), (1, "f32", (4, 10, 64)), (1, "f32", (3, 13, 128)), (1, "f32", (5, 6, 64)),
