@@ -85,8 +85,8 @@ enum ptrt_lattice { PTRT_D2Q9 = 0, PTRT_D3Q19 = 1, PTRT_D3Q27 = 2 };
  * PTRT_F16 / PTRT_BF16 round each store to nearest even.  PTRT_F16_SR /
  * PTRT_BF16_SR keep the same 16-bit formats but round each store of a step
  * stochastically (up with the probability given by the value's position
- * between its two neighbours; the dither is a hash of the value, so runs
- * are reproducible), which keeps small per-step changes from being lost
+ * between its two neighbours; the random bits are a hash of the value, so
+ * runs are reproducible), which keeps small per-step changes from being lost
  * systematically on fine lattices; the initial state and
  * ptrt_set_populations still round to nearest. */
 enum ptrt_storage {

@@ -78,24 +78,48 @@ struct Codec<bf16_t> {
     __device__ __forceinline__ static void store_nearest(bf16_t *p, float v) { *p = (bf16_t)v; }
 };
 
-// Stochastic rounding: v plus a uniform dither of one unit in the last
-// place of the target format (ulp_scale: 2^-mantissa bits; min_ulp: the
-// unit of its smallest exponent), then the conversion's round to nearest,
-// so that v rounds up with probability equal to its distance from the
-// lower neighbour in units of the gap.  The dither is a hash of v's bits
-// (deterministic: the same value always rounds the same way; a value that
-// changes in its low bits from one step to the next draws a new dither).
-__device__ __forceinline__ float sr_dither(float v, float ulp_scale, float min_ulp)
+// Stochastic rounding to a 16-bit format: a value between two neighbours
+// of the target rounds to the upper one (in magnitude) with probability
+// equal to its distance from the lower one in units of their gap.  Random
+// bits are added to the FP32 bit pattern below the target's last mantissa
+// bit and those bits are then cut off, so the carry into the kept bits
+// (and across a binade) happens with exactly that probability; the result
+// then converts exactly.  The random bits come from the value's own bits
+// (sr_bits): deterministic (the same value always rounds the same way),
+// while a value that changes from one step to the next draws new ones.
+// No branches: the stores of a step are not held up by divergent lanes.
+
+// Random bits: the value's bits times an odd constant, modulo 2^32
+// (multiplicative hashing), read from the top: for a fixed pattern of the
+// bits to be cut off, the top bits vary uniformly with the kept bits, so
+// over the values of a lattice the round-up frequency of each pattern is
+// its distance from the lower neighbour (unbiased); an exactly
+// representable value has nothing to cut and stays as it is.
+__device__ __forceinline__ unsigned sr_bits(unsigned b)
+{
+    return b * 0x9E3779B1u;
+}
+
+// FP16 (10 mantissa bits, normal from 2^-14): 13 bits cut off in the
+// normal range; below 2^-14 the gap is 2^-24 throughout, so a uniform
+// dither of one gap before the round to nearest does the same there.
+// Non-finite values pass unchanged; finite ones beyond the FP16 range
+// become infinite in the conversion.
+__device__ __forceinline__ float sr_to_f16_grid(float v)
+{
+    const unsigned b = __float_as_uint(v), a = b & 0x7FFFFFFFu, h = sr_bits(b);
+    const float cut = __uint_as_float((b + (h >> 19)) & ~0x1FFFu);
+    const float dith = fmaf((float)(h >> 8) * 0x1p-24f - 0.5f, 0x1p-24f, v);
+    return a >= 0x7F800000u ? v : (a >= 0x38800000u ? cut : dith);
+}
+
+// BF16 (the FP32 exponent range, 7 mantissa bits): 16 bits cut off for
+// every finite value, subnormals included.
+__device__ __forceinline__ float sr_to_bf16_grid(float v)
 {
     const unsigned b = __float_as_uint(v);
-    unsigned h = b * 0x9E3779B1u;
-    h ^= h >> 16;
-    h *= 0x85EBCA6Bu;
-    h ^= h >> 13;
-    const float r = (float)(h >> 8) * (1.0f / 16777216.0f) - 0.5f;
-    const float e2 = __uint_as_float(b & 0x7F800000u);
-    const float ulp = fmaxf(e2 * ulp_scale, min_ulp);
-    return fmaf(r, ulp, v);
+    const float cut = __uint_as_float((b + (sr_bits(b) >> 16)) & 0xFFFF0000u);
+    return (b & 0x7FFFFFFFu) >= 0x7F800000u ? v : cut;
 }
 
 struct f16sr_t {
@@ -114,7 +138,7 @@ struct Codec<f16sr_t> {
     template <bool NT = false>
     __device__ __forceinline__ static void store(f16sr_t *p, float v)
     {
-        const _Float16 hv = (_Float16)sr_dither(v, 0x1p-10f, 0x1p-24f);
+        const _Float16 hv = (_Float16)sr_to_f16_grid(v);
         if constexpr (NT) __builtin_nontemporal_store(hv, &p->v); else p->v = hv;
     }
     __device__ __forceinline__ static void store_nearest(f16sr_t *p, float v) { p->v = (_Float16)v; }
@@ -129,7 +153,7 @@ struct Codec<bf16sr_t> {
     template <bool NT = false>
     __device__ __forceinline__ static void store(bf16sr_t *p, float v)
     {
-        const bf16_t b = (bf16_t)sr_dither(v, 0x1p-7f, 0x1p-133f);
+        const bf16_t b = (bf16_t)sr_to_bf16_grid(v);
         if constexpr (NT) __builtin_nontemporal_store(b, &p->v); else p->v = b;
     }
     __device__ __forceinline__ static void store_nearest(bf16sr_t *p, float v) { p->v = (bf16_t)v; }

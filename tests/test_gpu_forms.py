@@ -312,7 +312,7 @@ def test_precision_form_512_against_fp64_storage():
 
 
 def test_stochastic_rounding_is_reproducible():
-    """Stochastic rounding draws its dither from the stored value itself:
+    """Stochastic rounding draws its random bits from the stored value itself:
     two runs give the same bits, and the result differs from round to
     nearest; the initial state is rounded to nearest in both."""
     print_case("stochastic rounding reproducible")
