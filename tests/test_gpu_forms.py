@@ -329,3 +329,51 @@ def test_stochastic_rounding_is_reproducible():
     assert np.array_equal(out["a"], out["b"])
     assert not np.array_equal(out["a"], out["rne"])
     assert np.array_equal(out["sr0"], out["rne0"])
+
+
+def _ordered16(bits):
+    """FP16 / BF16 bit patterns as integers in the order of their values:
+    neighbouring representable values are one apart, both zeros are 0."""
+    b = bits.astype(np.int32)
+    mag = b & 0x7FFF
+    return np.where(b & 0x8000, -mag, mag)
+
+
+def _stored_bits(f, storage):
+    """The stored 16-bit patterns of the shifted populations h = f - w (the
+    FP64 read-back is h + w in FP64, so the nearest 16-bit value of f - w is
+    h exactly)."""
+    _, w = P.ptrt_velocity_set(P.PTRT_D3Q19)
+    h = f - w[:, None, None, None]
+    if storage.startswith("f16"):
+        return h.astype(np.float16).view(np.uint16)
+    return (h.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("rne,sr", [("f16", "f16sr"), ("bf16", "bf16sr")])
+def test_stochastic_rounding_picks_a_neighbour(rne, sr):
+    """One step from the same state with round to nearest and with
+    stochastic rounding: the collision is the same FP32 code, so every
+    stochastically rounded value is the round-to-nearest result or the
+    representable value next to it, across binade boundaries and zero too;
+    the two differ in about a quarter of the values (the mean of min(p, 1 -
+    p) for a uniform position p between the neighbours), and the
+    stochastic choice moves up and down about equally often."""
+    print_case("stochastic rounding picks a neighbour", rne, sr)
+    n = 32
+    tp = I.tgv3d_params(n)["tau_plus"]
+    rho, u = I.tgv3d(n, 0.05)
+    bits = {}
+    for st in (rne, sr):
+        with P.Lattice(1, n, n, n, tp, 0.25, storage=st) as G:
+            G.init_equilibrium(rho, u)
+            G.step(1)
+            bits[st] = _stored_bits(G.populations(), st)
+    d = _ordered16(bits[sr]) - _ordered16(bits[rne])
+    differ = float(np.mean(d != 0))
+    up = float(np.mean(d[d != 0] > 0))
+    print(f"{sr}: {differ:.3f} of the values differ from {rne}, {up:.3f} of those upwards",
+          flush=True)
+    assert np.abs(d).max() <= 1
+    assert 0.15 < differ < 0.35
+    assert 0.45 < up < 0.55
