@@ -13,8 +13,11 @@
 // k - 2 when e_iz = +1, so LDS holds the e_z = -1 directions of one plane,
 // the e_z = 0 directions of two planes and the e_z = +1 directions of three
 // (38 direction planes of 66 x (BY + 2) nodes on D3Q19).  The workgroup
-// barriers order LDS only, so the loads of the next plane stay in flight
-// across them.  The A values pass through the storage type exactly as they
+// barriers order LDS only: they do not wait for global loads (in the FP32
+// pass the compiled loop still waits for the next plane's loads before its
+// first barrier, which measured faster than keeping them in flight across
+// it: loads issued further ahead evict halo lines from L2 before the
+// neighbouring columns read them).  The A values pass through the storage type exactly as they
 // would through HBM, so two steps of this kernel equal two steps of k_step
 // bit for bit.  A chunk recomputes the A planes just below and above it
 // (ZC + 2 A planes for ZC B planes).  Measured alternatives that lost:
@@ -23,7 +26,8 @@
 // writing the e_z >= 0 classes to LDS after the second step (24 instead of
 // 38 direction planes, three or four workgroups per CU); separate code
 // paths for the row and halo tasks; keeping in LDS only the 64 x 4 values
-// per direction that the second step reads (three workgroups per CU).
+// per direction that the second step reads (three workgroups per CU);
+// buffer loads and stores through per-plane descriptors.
 #pragma once
 
 #include "kernels.hpp"
