@@ -186,7 +186,6 @@ __device__ __forceinline__ C edot(C vx, C vy, C vz)
     return r;
 }
 
-// Density deviation and momentum of shifted populations.
 // 1 / rho.  FAST (chosen for FP32 storage): the hardware reciprocal refined
 // by one Newton step, within one unit in the last place, 3 instructions
 // instead of the correctly rounded division's 9 (measured +0.6-1 % on the
@@ -204,6 +203,7 @@ __device__ __forceinline__ C recip(C x)
     }
 }
 
+// Density deviation and momentum of shifted populations.
 template <class L, class C>
 __device__ __forceinline__ void shifted_moments(const C (&h)[L::Q], C &drho, C &jx, C &jy, C &jz)
 {
