@@ -423,11 +423,12 @@ inline bool step2_zoff_ok(const Geom &g)
     return (double)(g.ny >> g.lr) * (double)g.tile * (double)sizeof(S) < 4294967296.0;
 }
 
-// Grid (x blocks, y blocks, z chunks of zc planes), without solids.
+// Grid (x blocks, y blocks, z chunks of zc planes), without solids; the
+// launch covers workgroup rows by0 ... by0 + gridDim.y - 1.
 template <class L, class S, bool NT, int MODEL = MODEL_PTRT, bool ZOFF = false>
 __global__ void __launch_bounds__((64 * Step2Shape<L, S>::WAVES))
 k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
-        Coef<L, typename Codec<S>::compute> r, int zc)
+        Coef<L, typename Codec<S>::compute> r, int zc, int by0)
 {
     using SH = Step2Shape<L, S>;
     __shared__ S lds[SH::K::planes * SH::AP];
@@ -435,7 +436,7 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, Geom g,
     xcd_block(bx, by, bz);
     const int zs = bz * zc;
     step2_3d_task<L, S, NT, false, MODEL, ZOFF>(src, dst, nullptr, g, r, lds, bx * SH::BX,
-                                                by * SH::BY, zs, min(zs + zc, g.nz));
+                                                (by0 + by) * SH::BY, zs, min(zs + zc, g.nz));
 }
 
 // Task list (with solids): workgroup t runs tasks[t] = {x0, y0, zs, ze}.

@@ -73,19 +73,12 @@ inline int step2_2d_rows(int storage, int nx, int ny)
     return step2_2d_rows_for(storage, strips * ny, (long long)nx * ny);
 }
 
-// Planes per z chunk of the 3D two-step pass (grid or task list).
+// Workgroups of the 3D two-step pass resident at once on the device
+// (per CU, from the occupancy query, times the CUs).
 template <class L, class S>
-int step2_3d_zc(const Geom &g)
+int step2_3d_resident()
 {
     using SH = Step2Shape<L, S>;
-    // z chunks: the workgroups run in rounds of R = (workgroups
-    // resident per CU) x CUs, and a workgroup's time grows with
-    // its zc + 2 first-step planes, so zc minimises
-    // ceil(cols * ceil(nz / zc) / R) * (zc + 2) (measured at
-    // 384^3: 576 workgroups of the whole depth, 1.1 rounds,
-    // 34.9 GLUPS)
-    const int rows = (g.ny + SH::BY - 1) / SH::BY;
-    const long long cols = (long long)(g.nx / SH::BX) * rows;
     static int resident = 0; // per process: one device type
     if (resident == 0) {
         int per_cu = 0, dev = 0, cus = 0;
@@ -100,6 +93,23 @@ int step2_3d_zc(const Geom &g)
         else
             resident = per_cu * cus;
     }
+    return resident;
+}
+
+// Planes per z chunk of the 3D two-step pass (grid or task list).
+template <class L, class S>
+int step2_3d_zc(const Geom &g)
+{
+    using SH = Step2Shape<L, S>;
+    // z chunks: the workgroups run in rounds of R = (workgroups
+    // resident per CU) x CUs, and a workgroup's time grows with
+    // its zc + 2 first-step planes, so zc minimises
+    // ceil(cols * ceil(nz / zc) / R) * (zc + 2) (measured at
+    // 384^3: 576 workgroups of the whole depth, 1.1 rounds,
+    // 34.9 GLUPS)
+    const int rows = (g.ny + SH::BY - 1) / SH::BY;
+    const long long cols = (long long)(g.nx / SH::BX) * rows;
+    const int resident = step2_3d_resident<L, S>();
     // candidates: zc = ceil(nz / c) for c = 1, 2, ... chunks, down
     // to 8 planes or until the last round is under 1/16 of the
     // work (more chunks then only add halo planes)
@@ -267,8 +277,8 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                 const dim3 grid(a.g.nx / SH::BX, rows, (a.g.nz + zc - 1) / zc);
                 const dim3 block(64 * SH::WAVES, 1, 1);
                 // the state read once and written once: the first step's
-                // halo re-reads are L2 traffic when neighbouring columns run
-                // on one XCD (measured: HBM reads 1.03x the state)
+                // halo re-reads are mostly L2 traffic when neighbouring
+                // columns run on one XCD (the counters give the HBM reads)
                 if (pass_bytes) *pass_bytes = 2.0 * a.g.nx * a.g.ny * a.g.nz * L::Q * sizeof(S);
                 const Coef<L, C> r = make_coef<L, C>(a.tau_plus, a.Lambda, a.force);
                 // per-task source offsets where the layout allows (FP32)
@@ -304,15 +314,31 @@ bool launch_step2_lattice(const StepLaunch &a, double *pass_bytes)
                     });
                     go(std::true_type{}, std::false_type{}, a.tasks_special, a.n_special);
                 } else {
+                    // whole-depth columns that need more than one round of
+                    // resident workgroups: one launch per round's worth of
+                    // workgroup rows, so that every workgroup of a launch
+                    // starts at once and neighbouring columns stay near
+                    // the same plane (their shared halo lines then meet in
+                    // L2; a second round started as slots free up drifts)
+                    const int xb = a.g.nx / SH::BX;
+                    int slice = rows;
+                    const int resident = step2_3d_resident<L, S>();
+                    if (grid.z == 1 && (long long)xb * rows > resident)
+                        slice = std::max(1, resident / xb);
                     auto grid_pass = [&](auto modc, auto zc_) {
                         constexpr int MD = decltype(modc)::value;
                         constexpr bool Z = decltype(zc_)::value;
-                        if (a.nt)
-                            hipLaunchKernelGGL((k_step2<L, S, true, MD, Z>), grid, block, 0,
-                                               a.stream, (const S *)a.src, (S *)a.dst, a.g, r, zc);
-                        else
-                            hipLaunchKernelGGL((k_step2<L, S, false, MD, Z>), grid, block, 0,
-                                               a.stream, (const S *)a.src, (S *)a.dst, a.g, r, zc);
+                        for (int by0 = 0; by0 < rows; by0 += slice) {
+                            const dim3 gs(grid.x, std::min(slice, rows - by0), grid.z);
+                            if (a.nt)
+                                hipLaunchKernelGGL((k_step2<L, S, true, MD, Z>), gs, block, 0,
+                                                   a.stream, (const S *)a.src, (S *)a.dst, a.g,
+                                                   r, zc, by0);
+                            else
+                                hipLaunchKernelGGL((k_step2<L, S, false, MD, Z>), gs, block, 0,
+                                                   a.stream, (const S *)a.src, (S *)a.dst, a.g,
+                                                   r, zc, by0);
+                        }
                     };
                     with_zoff([&](auto zc_) {
                         if (a.model == MODEL_TRT_RLB)
