@@ -47,6 +47,11 @@ def _run(lat, shape, storage, steps, spp, mask=None, force=None, seed=5, passes=
     # chunks of 1, 2, 5 and 7 planes, and several chunks per column
     (1, "f64", (1, 8, 64)), (1, "f64", (2, 8, 64)), (1, "f64", (5, 6, 64)), (1, "f64", (7, 16, 128)),
     (1, "f64", (128, 128, 128)), (1, "f64", (99, 64, 64)),
+    # more whole-depth columns than one round of resident workgroups (on
+    # MI355X 512 in FP32, 256 in FP64): one launch per round's worth of
+    # workgroup rows, the last one short (600 rows as 512 + 88, 300 as
+    # 256 + 44)
+    (1, "f32", (4, 2400, 64)), (1, "f64", (4, 1200, 64)),
     (1, "f16", (5, 16, 64)), (1, "bf16", (9, 8, 128)),
     (2, "f16", (9, 8, 64)), (2, "bf16", (4, 12, 64))])
 @pytest.mark.parametrize("steps", [1, 2, 7, 40])
