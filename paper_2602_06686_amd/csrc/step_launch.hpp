@@ -79,8 +79,9 @@ template <class L, class S>
 int step2_3d_resident()
 {
     using SH = Step2Shape<L, S>;
-    static int resident = 0; // per process: one device type
-    if (resident == 0) {
+    // queried once per process (one device type), by a thread-safe static
+    // initialisation: handles used from several threads may get here at once
+    static const int resident = [] {
         int per_cu = 0, dev = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &per_cu, reinterpret_cast<const void *>(&k_step2<L, S, true>),
@@ -89,10 +90,9 @@ int step2_3d_resident()
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                 hipSuccess ||
             per_cu <= 0 || cus <= 0)
-            resident = 512;
-        else
-            resident = per_cu * cus;
-    }
+            return 512;
+        return per_cu * cus;
+    }();
     return resident;
 }
 
