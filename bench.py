@@ -28,7 +28,9 @@ and a plain streaming kernel's bandwidth measured beside it.  ``traffic`` is
 read from the committed rocprofv3 counter summary when it was taken on the
 current kernel sources, else null.  ``cpu_baseline`` times the FP64 C oracle
 on twelve steps of the same 256^3 lattice on the host cores (and on one
-thread).
+thread), and under ``other_workloads`` on bounded samples of the D2Q9
+forms (the 64^2 vortex in full, 10 steps of the 2048^2 shear layer, 2
+steps of each batch lattice).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only FORM]
                        [--no-cpu] [--copy-calibration]
